@@ -1,0 +1,91 @@
+"""Host setup: the QTT operators equal the checker's dense operators."""
+import numpy as np
+import pytest
+
+from oracle import dense, tt as OT
+from paper_2309_03347_amd import operators as O, qtt, solver as SV, workload as W
+
+
+def _bidiag_dense(n, a, c, lower):
+    J = np.eye(n, k=-1) if lower else np.eye(n, k=1)
+    return a * np.eye(n) + c * J
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 5])
+def test_closed_form_qtt_bidiagonal(l):
+    n = 1 << l
+    for lower in (True, False):
+        cores = qtt.qtt_bidiag(l, 0.3, -1.7, lower)
+        assert np.allclose(OT.full_mat(cores), _bidiag_dense(n, 0.3, -1.7, lower))
+        assert max(c.shape[-1] for c in cores) <= 2
+
+
+@pytest.mark.parametrize("l", [1, 3, 6])
+def test_qtt_matches_tt_svd_ranks(l):
+    # Algorithm TTtoQTT (reshape, pair (i_b, j_b), TT-SVD) gives the same ranks.
+    n = 1 << l
+    h = 1.0 / (n - 1)
+    for mat in (dense.diff_matrix(n, h, True), dense.interp_matrix(n, False, True)):
+        t = mat.reshape((2,) * (2 * l))
+        perm = [x for b in range(l) for x in (b, l + b)]
+        t = t.transpose(perm).reshape((4,) * l)
+        svd_ranks = [c.shape[-1] for c in qtt.tt_svd(t, 1e-13)]
+        if np.allclose(mat, dense.diff_matrix(n, h, True)):
+            ours = qtt.tt_round_host(qtt.qtt_bidiag(l, 1 / h, -1 / h, True), 1e-13)
+        else:
+            ours = qtt.tt_round_host(O._interp(l, False, True), 1e-13)
+        assert [c.shape[-1] for c in ours] == svd_ranks
+        assert np.allclose(OT.full_mat(ours), mat)
+
+
+@pytest.mark.parametrize("l,lo,hi", [(3, 0, 7), (3, 2, 5), (4, 5, 5), (5, 1, 30), (4, 0, 0)])
+def test_interval_indicator(l, lo, hi):
+    v = OT.full_vec(qtt.qtt_interval(l, lo, hi))
+    ref = np.zeros(1 << l)
+    ref[lo:hi + 1] = 1
+    assert np.array_equal(v, ref)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.homogeneous(l=2, N=2, seed=0),
+    lambda: W.homogeneous(l=2, N=4, seed=1),
+    lambda: W.inner_box(l=2, G=2, N=2, seed=3),
+    lambda: W.checkerboard(l=2, G=2, N=2, blocks=2, n_mat=3, seed=5),
+])
+def test_operators_equal_dense_tt_form(maker):
+    wl = maker()
+    Ht, St, Ft = dense.tt_form_operators(wl)
+    Hu, Su, Fu = O.build_unrounded(wl)
+    for mine, ref in ((Hu, Ht), (Su, St), (Fu, Ft)):
+        assert np.abs(OT.full_mat(mine) - ref.toarray()).max() < 1e-12 * max(1.0, abs(ref).max())
+    ops = O.build(wl)
+    for mine, ref in ((ops.H, Ht), (ops.S, St), (ops.F, Ft)):
+        assert np.abs(OT.full_mat(mine) - ref.toarray()).max() < 1e-11 * max(1.0, abs(ref).max())
+    assert np.allclose(OT.full_vec(ops.cF), Ft.toarray().sum(axis=0), atol=1e-12)
+
+
+def test_interior_rows_equal_cell_equations():
+    wl = W.inner_box(l=2, G=2, N=2, seed=6)
+    H, S, F = dense.equation_operators(wl)
+    ops = O.build(wl)
+    idx = dense.cell_row_index(wl)
+    Hq = OT.full_mat(ops.H)
+    assert np.abs(Hq[idx] - H[idx].toarray()).max() < 1e-11
+
+
+def test_joint_rhs_operator():
+    wl = W.inner_box(l=2, G=3, N=2, seed=7)
+    ops = O.build(wl)
+    SF, F0 = SV.joint_rhs_operator(ops.S, ops.F)
+    k = 0.61
+    A = [SF[0] + F0 / k] + SF[1:]
+    ref = OT.full_mat(ops.S) + OT.full_mat(ops.F) / k
+    assert np.abs(OT.full_mat(A) - ref).max() < 1e-12
+    assert max(qtt.ranks(SF)) <= max(qtt.ranks(ops.S)) + max(qtt.ranks(ops.F))
+
+
+def test_initial_flux_matches_dense_start():
+    from oracle import sweep
+    wl = W.inner_box(l=2, G=2, N=4, seed=8)
+    ops = O.build(wl)
+    assert np.allclose(OT.full_vec(ops.psi0), sweep.dense_psi0(wl))
