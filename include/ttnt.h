@@ -1,0 +1,236 @@
+/*
+ * ttnt.h - C ABI of the MI355X tensor-train k-eigenvalue library (libttnt.so).
+ *
+ * The library runs, on one gfx950 GPU, the per-iteration work of the mixed
+ * TT/QTT power iteration for the discretized transport eigenproblem
+ *     H psi = (S + F / k) psi                          (eq. OpFormkNTE)
+ * iterated as
+ *     B_t      = (S + F / k_t) psi_t
+ *     H psi_t+1 = B_t
+ *     k_t+1    = k_t * sum(F psi_t+1) / sum(F psi_t)  (eq. TT_k_eff_fixed_points)
+ * with H, S, F tensor-train (TT) matrices and psi a TT vector (Section 2.2,
+ * eqs. TT-vector and TT-matrix-componentwise).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Numbers are IEEE binary64 unless a field says otherwise.
+ *  - A TT vector with d cores stores core k as a dense row-major array
+ *    [r_k][n_k][r_{k+1}] (last index fastest), r_0 = r_d = 1.  Core k begins
+ *    at data + off[k] (element offset) and may use up to
+ *    rcap[k] * n[k] * rcap[k+1] elements (its capacity slot); the core in use
+ *    is packed at the start of the slot with its actual ranks r[].
+ *  - A TT matrix core k is [R_k][m_k][n_k][R_{k+1}], m = row (output) mode,
+ *    n = column (input) mode, packed at data + off[k].
+ *  - `data` pointers are device pointers; every other pointer in a descriptor
+ *    is a host pointer.  All buffers belong to the caller; entry points do
+ *    not keep pointers after they return, except a tt_solver, which owns the
+ *    device copies it makes at creation.
+ *  - Calls are enqueued on `stream`.  Entry points that decide ranks on the
+ *    device (tt_round, tt_local_solve, tt_power_step) synchronize `stream`
+ *    before returning, because the chosen ranks size later launches.
+ *  - Errors are returned as tt_status; nothing is thrown across the ABI.
+ *    On TT_E_ARG / TT_E_CAPACITY / TT_E_DTYPE nothing is written.
+ *    tt_last_error() returns a message for the last failure on this thread.
+ */
+#ifndef TTNT_H_
+#define TTNT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tt_status;
+#define TT_OK 0
+#define TT_E_ARG (-1)       /* bad descriptor, shape or option */
+#define TT_E_CAPACITY (-2)  /* output ranks exceed the caller's capacity */
+#define TT_E_NOCONV (-3)    /* iteration limit reached; result written */
+#define TT_E_NUMERIC (-4)   /* NaN or Inf detected */
+#define TT_E_DTYPE (-5)     /* unsupported number type */
+#define TT_E_HIP (-6)       /* HIP runtime error */
+
+typedef struct ihipStream_t* tt_stream; /* hipStream_t; NULL = default stream */
+
+typedef struct {
+  int32_t d;             /* number of cores, >= 1 */
+  const int32_t* n;      /* [d] mode sizes */
+  int32_t* r;            /* [d+1] ranks; input, and output where stated */
+  const int32_t* rcap;   /* [d+1] capacity ranks of the slots (rcap >= r) */
+  double* data;          /* device base pointer */
+  const int64_t* off;    /* [d] element offset of each core slot */
+} tt_vec;
+
+typedef struct {
+  int32_t d;
+  const int32_t* m;      /* [d] row (output) mode sizes */
+  const int32_t* n;      /* [d] column (input) mode sizes */
+  const int32_t* R;      /* [d+1] ranks, R_0 = R_d = 1 */
+  const double* data;    /* device base pointer */
+  const int64_t* off;    /* [d] element offset of each core */
+} tt_mat;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t ttnt_version(void);
+/* Message describing the last error returned on the calling thread. */
+const char* tt_last_error(void);
+
+/*
+ * tt_matvec - exact TT-matrix x TT-vector product y = A x.
+ *
+ * Core contraction of Oseledets' TT matrix-by-vector product (Section 2.2,
+ * "Linear Operators in TT format"; the explicit exact algorithm named in
+ * Section 3.3):
+ *     Y_k[(b,a), i, (b',a')] = sum_j A_k[b, i, j, b'] X_k[a, j, a'],
+ * so y has ranks R_k * r_k and modes m_k.  Row index (b,a) = b * r_k + a.
+ * Requires A->n[k] == x->n[k] and y->n[k] == A->m[k] for every k, and
+ * y->rcap[k] >= A->R[k] * x->r[k]; otherwise TT_E_ARG / TT_E_CAPACITY.
+ * Writes y->r.  Asynchronous on `stream`.
+ */
+tt_status tt_matvec(const tt_mat* A, const tt_vec* x, tt_vec* y, tt_stream stream);
+
+/*
+ * tt_round - in-place TT rounding (rank truncation with an error bound).
+ *
+ * A left-to-right sweep of Householder QR factorizations (each core made
+ * left-orthonormal, R pushed into the next core), then a right-to-left
+ * sweep of truncated SVDs that keeps, at every bond, the fewest singular
+ * values whose discarded tail has norm <= tol * ||x|| / sqrt(d-1), capped at
+ * rmax.  Rank reduction after sums and products is the step named in
+ * Section 2.2 ("a rank reduction step could be necessary").  Guarantees
+ * ||x_in - x_out|| <= tol * ||x_in|| unless rmax binds (not an error).
+ * rel_err (host, may be NULL) receives sqrt(sum of discarded sigma^2)/||x||.
+ * `ws` is device workspace of at least tt_round_workspace(x) bytes.
+ * Updates x->r.  Synchronizes `stream`.
+ */
+size_t tt_round_workspace(const tt_vec* x);
+tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* ws,
+                   size_t ws_bytes, tt_stream stream);
+
+/*
+ * tt_dot - inner product <a, b> of two TT vectors with equal modes
+ * (sequential contraction of the core pairs).  result: host double.
+ * `ws` device workspace of tt_dot_workspace(a, b) bytes.  Synchronizes.
+ */
+size_t tt_dot_workspace(const tt_vec* a, const tt_vec* b);
+tt_status tt_dot(const tt_vec* a, const tt_vec* b, double* result, void* ws, size_t ws_bytes,
+                 tt_stream stream);
+
+/*
+ * tt_local_solve - the projected local linear system of the alternating
+ * (ALS / AMEn) solve of A x = f for core k (Section 3.3, eq.
+ * TT_min_LS_problem; Galerkin projection onto the left and right orthonormal
+ * interfaces of the current iterate):
+ *     sum_{b,b'} PhiL[:, b, :] (x) A_k[b, :, :, b'] (x) PhiR[:, b', :]  x_k = f_k
+ * Shapes: PhiL [ra][RL][ra], A_k [RL][m][n][RR] with m == n, PhiR [rc][RR][rc],
+ * f and x [ra][n][rc] (all device, row-major).  x holds the initial guess
+ * on input and the solution on output.  method: 0 automatic (dense LU when
+ * ra*n*rc <= direct_max, else restarted GMRES), 1 dense LU with partial
+ * pivoting, 2 GMRES.  info (host) receives iterations and the final relative
+ * residual ||A x - f|| / ||f||.  Returns TT_E_NOCONV if GMRES stops at
+ * max_iter above tol (x still written).  Synchronizes `stream`.
+ */
+typedef struct {
+  int32_t ra, RL, m, n, RR, rc;
+  const double* phiL;
+  const double* A;
+  const double* phiR;
+  const double* f;
+} tt_local;
+
+typedef struct {
+  int32_t method;       /* 0 auto, 1 LU, 2 GMRES */
+  double tol;           /* relative residual target for GMRES */
+  int32_t max_iter;     /* total GMRES iterations */
+  int32_t restart;      /* Krylov dimension per cycle */
+  int32_t direct_max;   /* auto: LU up to this many unknowns */
+} tt_solve_opts;
+
+typedef struct {
+  int32_t iterations;
+  int32_t method_used;
+  double rel_res;
+} tt_solve_info;
+
+size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts);
+tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
+                         tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream);
+
+/*
+ * Power-iteration solver (one call of tt_power_step = one step of
+ * eq. TT_k_eff_fixed_points).
+ *
+ * Problem: H (transport operator), and S + F/k given as one TT matrix `SF`
+ * whose cores 1..d-1 are shared by S and F and whose core 0 is the S part;
+ * `F_core0` (device, the shape of SF core 0) is the F part, so that
+ * core 0 of S + F/k is SF_0 + F_core0 / k.  `cF` is the TT vector F^T 1 so
+ * that sum(F psi) = <cF, psi> (eq. TT_k_eff_fixed_points, last line).
+ * `psi0` is the start vector and k0 the start eigenvalue.
+ *
+ * Each step:
+ *   1. right-hand side: rhs_mode 1 forms B = tt_matvec(S + F/k, psi) and
+ *      rounds it (tt_round, tol, rhs_rmax); rhs_mode 0 projects
+ *      (S + F/k) psi onto the solve's interfaces core by core without
+ *      forming B (the projected matrix-vector product of eq. mv_obj);
+ *   2. AMEn sweeps for H psi+ = B with psi as the initial guess (Galerkin
+ *      local systems by tt_local_solve, truncated SVD of each solved core,
+ *      residual-based enrichment of rank `kick`), at most max_sweeps, until
+ *      the largest local relative residual before a solve is below tol;
+ *   3. psi+ rounded to (tol, rmax);
+ *   4. k+ = k * <cF, psi+> / <cF, psi>; psi+ scaled to unit 2-norm.
+ * The solver copies all problem data to device memory it allocates at
+ * creation (hipMalloc happens only in tt_solver_create).
+ */
+typedef struct {
+  tt_mat H;
+  tt_mat SF;
+  const double* F_core0;
+  tt_vec cF;
+  tt_vec psi0;
+  double k0;
+} tt_problem;
+
+typedef struct {
+  double tol;            /* truncation tolerance (relative, Frobenius) */
+  int32_t rmax;          /* rank cap of psi */
+  int32_t kick;          /* AMEn enrichment rank */
+  int32_t max_sweeps;    /* AMEn sweeps per power step */
+  int32_t rhs_mode;      /* 0 projected, 1 explicit matvec + rounding */
+  int32_t rhs_rmax;      /* rank cap of the explicit B */
+  double local_tol;      /* relative tolerance of local solves (0: tol / sqrt(d)) */
+  int32_t gmres_restart;
+  int32_t gmres_max_iter;
+  int32_t direct_max;    /* local systems up to this size use dense LU */
+} tt_solver_opts;
+
+typedef struct {
+  double k;              /* k after the step */
+  double k_prev;         /* k before the step */
+  double dk;             /* |k - k_prev| */
+  double max_local_res;  /* largest local residual seen before a solve (last sweep) */
+  double trunc_err;      /* relative truncation error of the final rounding */
+  int32_t sweeps;        /* AMEn sweeps performed */
+  int32_t max_rank;      /* largest rank of psi after the step */
+  int32_t local_iters;   /* GMRES iterations summed over the step */
+  int32_t status;        /* TT_OK, or TT_E_NOCONV if the sweep limit was hit */
+} tt_step_info;
+
+typedef struct tt_solver_s tt_solver;
+
+tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
+                           tt_solver** out);
+tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);
+/* Copy the current psi into the caller's TT vector (capacity checked); writes out->r. */
+tt_status tt_solver_get_psi(tt_solver* s, tt_vec* out, tt_stream stream);
+/* Current ranks of psi (host array of d+1) and d. */
+tt_status tt_solver_ranks(tt_solver* s, int32_t* ranks, int32_t* d);
+/* Number of kernel launches issued by the last tt_power_step (diagnostic). */
+int64_t tt_solver_launches(tt_solver* s);
+tt_status tt_solver_destroy(tt_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTNT_H_ */

@@ -1,0 +1,288 @@
+// extern "C" entry points of libttnt.so (declared in include/ttnt.h).
+#include <cmath>
+#include <exception>
+#include <string>
+
+#include "engine.h"
+#include "kernels.h"
+#include "solver.h"
+#include "ttk.h"
+
+using namespace ttnt;
+
+struct tt_solver_s {
+  Solver impl;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+tt_status guard(F&& f) {
+  try {
+    f();
+    return TT_OK;
+  } catch (const CapacityError& e) {
+    g_err = e.msg;
+    return TT_E_CAPACITY;
+  } catch (const ArgError& e) {
+    g_err = e.msg;
+    return TT_E_ARG;
+  } catch (const HipError& e) {
+    g_err = std::string("HIP error '") + hipGetErrorString(e.err) + "' in " + e.where;
+    return TT_E_HIP;
+  } catch (const NoConvError&) {
+    g_err = "iteration limit reached before the tolerance";
+    return TT_E_NOCONV;
+  } catch (const NumericError&) {
+    g_err = "non-finite value detected";
+    return TT_E_NUMERIC;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return TT_E_ARG;
+  } catch (...) {
+    g_err = "unknown failure";
+    return TT_E_ARG;
+  }
+}
+
+void check_vec(const tt_vec* v, const char* name) {
+  const std::string nm(name);
+  TT_REQUIRE(v != nullptr, nm + " is NULL");
+  TT_REQUIRE(v->d >= 1, nm + ": d must be >= 1");
+  TT_REQUIRE(v->n && v->r && v->rcap && v->off && v->data, nm + ": NULL field");
+  TT_REQUIRE(v->r[0] == 1 && v->r[v->d] == 1, nm + ": boundary ranks must be 1");
+  for (int k = 0; k < v->d; ++k) TT_REQUIRE(v->n[k] >= 1, nm + ": mode size < 1");
+  for (int k = 0; k <= v->d; ++k) {
+    TT_REQUIRE(v->r[k] >= 1, nm + ": rank < 1");
+    TT_REQUIRE(v->rcap[k] >= v->r[k], nm + ": rank exceeds its capacity");
+  }
+}
+
+void check_mat(const tt_mat* m, const char* name) {
+  const std::string nm(name);
+  TT_REQUIRE(m != nullptr, nm + " is NULL");
+  TT_REQUIRE(m->d >= 1, nm + ": d must be >= 1");
+  TT_REQUIRE(m->m && m->n && m->R && m->off && m->data, nm + ": NULL field");
+  TT_REQUIRE(m->R[0] == 1 && m->R[m->d] == 1, nm + ": boundary ranks must be 1");
+  for (int k = 0; k < m->d; ++k) TT_REQUIRE(m->m[k] >= 1 && m->n[k] >= 1, nm + ": mode size < 1");
+  for (int k = 0; k <= m->d; ++k) TT_REQUIRE(m->R[k] >= 1, nm + ": rank < 1");
+}
+
+LocalOp local_op_from(const tt_local* sys) {
+  LocalOp op{};
+  op.phiL = sys->phiL;
+  op.ra = op.rb = sys->ra;
+  op.RL = sys->RL;
+  op.A = sys->A;
+  op.m = sys->m;
+  op.n = sys->n;
+  op.RR = sys->RR;
+  op.phiR = sys->phiR;
+  op.rc = op.rd = sys->rc;
+  return op;
+}
+
+LocalSolveOpts solve_opts_from(const tt_solve_opts* o) {
+  LocalSolveOpts so;
+  if (o) {
+    so.method = o->method;
+    so.tol = o->tol > 0 ? o->tol : 1e-12;
+    so.max_iter = o->max_iter > 0 ? o->max_iter : 1000;
+    so.restart = o->restart > 0 ? o->restart : 80;
+    so.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
+  }
+  return so;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ttnt_version(void) { return 10000; }
+
+const char* tt_last_error(void) { return g_err.c_str(); }
+
+tt_status tt_matvec(const tt_mat* A, const tt_vec* x, tt_vec* y, tt_stream stream) {
+  return guard([&] {
+    check_mat(A, "A");
+    check_vec(x, "x");
+    TT_REQUIRE(y && y->n && y->r && y->rcap && y->off && y->data, "y: NULL field");
+    TT_REQUIRE(A->d == x->d && y->d == A->d, "core counts differ");
+    for (int k = 0; k < A->d; ++k) {
+      TT_REQUIRE(A->n[k] == x->n[k], "A column modes differ from x modes");
+      TT_REQUIRE(y->n[k] == A->m[k], "y modes differ from A row modes");
+    }
+    for (int k = 0; k <= A->d; ++k)
+      if (y->rcap[k] < A->R[k] * x->r[k]) throw CapacityError{"y capacity below R_k * r_k"};
+    TTm a = view(A);
+    TTv xv = view(x);
+    TTv yv;
+    yv.d = y->d;
+    yv.n.assign(y->n, y->n + y->d);
+    yv.r.assign(y->d + 1, 1);
+    yv.rcap.assign(y->rcap, y->rcap + y->d + 1);
+    yv.data = y->data;
+    yv.off.assign(y->off, y->off + y->d);
+    matvec((hipStream_t)stream, a, xv, yv);
+    for (int k = 0; k <= A->d; ++k) y->r[k] = yv.r[k];
+  });
+}
+
+size_t tt_round_workspace(const tt_vec* x) {
+  if (!x || x->d < 1 || !x->r || !x->n) return 0;
+  TTv t;
+  t.d = x->d;
+  t.n.assign(x->n, x->n + x->d);
+  t.r.assign(x->r, x->r + x->d + 1);
+  return round_ws_bytes(t);
+}
+
+tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* ws,
+                   size_t ws_bytes, tt_stream stream) {
+  return guard([&] {
+    check_vec(x, "x");
+    TT_REQUIRE(tol >= 0.0 && std::isfinite(tol), "tol must be finite and >= 0");
+    TT_REQUIRE(rmax >= 1, "rmax must be >= 1");
+    TT_REQUIRE(ws != nullptr, "workspace is NULL");
+    TTv t = view(x);
+    if (ws_bytes < round_ws_bytes(t)) throw CapacityError{"workspace smaller than tt_round_workspace"};
+    Bump b;
+    b.base = (char*)ws;
+    b.cap = ws_bytes;
+    round_tt((hipStream_t)stream, t, tol, rmax, rel_err, b);
+    TT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];
+  });
+}
+
+size_t tt_dot_workspace(const tt_vec* a, const tt_vec* b) {
+  if (!a || !b || a->d < 1 || a->d != b->d) return 0;
+  TTv ta, tb;
+  ta.d = tb.d = a->d;
+  ta.n.assign(a->n, a->n + a->d);
+  ta.r.assign(a->r, a->r + a->d + 1);
+  tb.n = ta.n;
+  tb.r.assign(b->r, b->r + b->d + 1);
+  return dot_ws_bytes(ta, tb) + 256;
+}
+
+tt_status tt_dot(const tt_vec* a, const tt_vec* b, double* result, void* ws, size_t ws_bytes,
+                 tt_stream stream) {
+  return guard([&] {
+    check_vec(a, "a");
+    check_vec(b, "b");
+    TT_REQUIRE(a->d == b->d, "core counts differ");
+    for (int k = 0; k < a->d; ++k) TT_REQUIRE(a->n[k] == b->n[k], "modes differ");
+    TT_REQUIRE(result && ws, "NULL result or workspace");
+    TTv ta = view(a), tb = view(b);
+    if (ws_bytes < dot_ws_bytes(ta, tb) + 256) throw CapacityError{"workspace smaller than tt_dot_workspace"};
+    Bump w;
+    w.base = (char*)ws;
+    w.cap = ws_bytes;
+    double* out = w.d(1);
+    dot_tt((hipStream_t)stream, ta, tb, out, w);
+    TT_HIP(hipMemcpyAsync(result, out, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    TT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
+size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts) {
+  if (!sys) return 0;
+  LocalOp op = local_op_from(sys);
+  LocalSolveOpts so = solve_opts_from(opts);
+  const size_t ap = (size_t)sys->RL * sys->m * sys->n * sys->RR;
+  return (local_solve_ws_doubles(op, so) + ap + 64) * sizeof(double) + 8192;
+}
+
+tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
+                         tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream) {
+  return guard([&] {
+    TT_REQUIRE(sys && x && ws, "NULL system, x or workspace");
+    TT_REQUIRE(sys->phiL && sys->A && sys->phiR && sys->f, "NULL field in system");
+    TT_REQUIRE(sys->ra >= 1 && sys->RL >= 1 && sys->m >= 1 && sys->n >= 1 && sys->RR >= 1 &&
+                   sys->rc >= 1,
+               "dimensions must be >= 1");
+    TT_REQUIRE(sys->m == sys->n, "local operator must be square (m == n)");
+    LocalSolveOpts so = solve_opts_from(opts);
+    TT_REQUIRE(so.method >= 0 && so.method <= 2, "method must be 0, 1 or 2");
+    if (ws_bytes < tt_local_solve_workspace(sys, opts))
+      throw CapacityError{"workspace smaller than tt_local_solve_workspace"};
+    hipStream_t s = (hipStream_t)stream;
+    Bump w;
+    w.base = (char*)ws;
+    w.cap = ws_bytes;
+    double* Ap = w.d((size_t)sys->RL * sys->m * sys->n * sys->RR);
+    permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
+    LocalOp op = local_op_from(sys);
+    op.Ap = Ap;
+    LocalSolveResult r = local_solve(s, op, sys->f, x, so, w, true);
+    if (info) {
+      info->iterations = r.iterations;
+      info->method_used = r.method;
+      info->rel_res = r.rel_res;
+    }
+    if (!std::isfinite(r.rel_res)) throw NumericError{};
+    if (!r.converged) throw NoConvError{};
+  });
+}
+
+tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
+                           tt_solver** out) {
+  return guard([&] {
+    TT_REQUIRE(problem && opts && out, "NULL argument");
+    check_mat(&problem->H, "H");
+    check_mat(&problem->SF, "SF");
+    check_vec(&problem->cF, "cF");
+    check_vec(&problem->psi0, "psi0");
+    auto* s = new tt_solver_s();
+    try {
+      s->impl.create(problem, opts);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream) {
+  tt_status st = guard([&] {
+    TT_REQUIRE(s != nullptr, "NULL solver");
+    s->impl.step((hipStream_t)stream, info);
+  });
+  if (st == TT_OK && info && info->status == TT_E_NOCONV) return TT_E_NOCONV;
+  return st;
+}
+
+tt_status tt_solver_get_psi(tt_solver* s, tt_vec* out, tt_stream stream) {
+  return guard([&] {
+    TT_REQUIRE(s && out && out->n && out->r && out->rcap && out->off && out->data, "NULL argument");
+    const TTv& p = s->impl.psi;
+    TT_REQUIRE(out->d == p.d, "core count differs");
+    for (int k = 0; k < p.d; ++k) TT_REQUIRE(out->n[k] == p.n[k], "modes differ");
+    for (int k = 0; k <= p.d; ++k)
+      if (out->rcap[k] < p.r[k]) throw CapacityError{"output capacity below the flux ranks"};
+    for (int k = 0; k < p.d; ++k) copy((hipStream_t)stream, p.core(k), out->data + out->off[k], p.size(k));
+    for (int k = 0; k <= p.d; ++k) out->r[k] = p.r[k];
+    TT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
+tt_status tt_solver_ranks(tt_solver* s, int32_t* ranks, int32_t* d) {
+  return guard([&] {
+    TT_REQUIRE(s && ranks && d, "NULL argument");
+    *d = s->impl.d;
+    for (int k = 0; k <= s->impl.d; ++k) ranks[k] = s->impl.psi.r[k];
+  });
+}
+
+int64_t tt_solver_launches(tt_solver* s) { return s ? s->impl.last_launches : -1; }
+
+tt_status tt_solver_destroy(tt_solver* s) {
+  delete s;
+  return TT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+// Dense FP64 building blocks: batched GEMM, copies, reductions.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace ttnt {
+
+thread_local int64_t g_launches = 0;
+thread_local double* g_splitk_buf = nullptr;
+thread_local size_t g_splitk_cap = 0;
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, GT = 256;
+
+// 64x64 output tile per workgroup of 256 threads; each thread owns a 4x4
+// block (rows tr*4+i, columns tc+16*j so that C stores are coalesced).
+// With nsplit > 1 the workgroup sums only its slice of K and stores the raw
+// partial tile to C + (split * batch + b) * M * N (dense, ld N); a second
+// kernel reduces the slices in a fixed order (deterministic).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, double alpha,
+                                                  const double* __restrict__ A, int lda,
+                                                  int64_t sA, const double* __restrict__ B,
+                                                  int ldb, int64_t sB, double beta,
+                                                  double* __restrict__ C, int ldc, int64_t sC,
+                                                  int nsplit, int kchunk, int batch) {
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int64_t bz = blockIdx.z % batch;
+  const int split = blockIdx.z / batch;
+  A += bz * sA;
+  B += bz * sB;
+  const int kb = split * kchunk;
+  const int ke = min(K, kb + kchunk);
+  if (nsplit > 1) {
+    C += ((int64_t)split * batch + bz) * M * N;
+    ldc = N;
+  } else {
+    C += bz * sC;
+  }
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+    for (int t = 0; t < (BM * BK) / GT; ++t) {
+      const int e = tid + t * GT;
+      int mm, kk;
+      if (!TA) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < ke) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < (BK * BN) / GT; ++t) {
+      const int e = tid + t * GT;
+      int kk, nn;
+      if (!TB) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
+      const int gk = k0 + kk, gn = n0 + nn;
+      double v = 0.0;
+      if (gk < ke && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + tr * 4 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tc + 16 * j;
+      if (gn >= N) continue;
+      double* c = C + (int64_t)gm * ldc + gn;
+      if (nsplit > 1) *c = acc[i][j];
+      else *c = beta == 0.0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * *c;
+    }
+  }
+}
+
+// C[b][m][n] = alpha * sum_s P[s][b][m][n] + beta * C[b][m][n]  (fixed order in s)
+__global__ void splitk_reduce_kernel(const double* __restrict__ P, int nsplit, int batch, int M,
+                                     int N, double alpha, double beta, double* __restrict__ C,
+                                     int ldc, int64_t sC) {
+  const int64_t per = (int64_t)M * N;
+  const int64_t total = per * batch;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, r = e % per;
+    const int m = (int)(r / N), n = (int)(r % N);
+    double acc = 0.0;
+    for (int s = 0; s < nsplit; ++s) acc += P[((int64_t)s * batch + b) * per + r];
+    double* c = C + b * sC + (int64_t)m * ldc + n;
+    *c = beta == 0.0 ? alpha * acc : alpha * acc + beta * *c;
+  }
+}
+
+__global__ void transpose_kernel(const double* __restrict__ src, int rows, int cols, int lds,
+                                 double* __restrict__ dst, int ldd) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, c = c0 + tx;
+    tile[y][tx] = (r < rows && c < cols) ? src[(int64_t)r * lds + c] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int c = c0 + y, r = r0 + tx;
+    if (c < cols && r < rows) dst[(int64_t)c * ldd + r] = tile[tx][y];
+  }
+}
+
+__global__ void copy2d_kernel(const double* __restrict__ src, int rows, int cols, int lds,
+                              double* __restrict__ dst, int ldd) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    dst[(int64_t)r * ldd + c] = src[(int64_t)r * lds + c];
+  }
+}
+
+__global__ void fill_kernel(double* dst, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = v;
+}
+
+__global__ void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b,
+                             const double* __restrict__ c, double* __restrict__ y) {
+  const double bb = c ? b / *c : b;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    y[e] = a * x[e] + bb * y[e];
+}
+
+__global__ __launch_bounds__(1024) void sumsq_kernel(const double* __restrict__ x, int64_t n,
+                                                     double* out) {
+  __shared__ double red[16];
+  double v = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) v = fma(x[e], x[e], v);
+  v = block_sum(v, red);
+  if (threadIdx.x == 0) *out = v;
+}
+
+__global__ void scale_inv_sqrt_kernel(double* x, int64_t n, const double* ss) {
+  const double f = 1.0 / sqrt(*ss);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] *= f;
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          int lda, int64_t sA, const double* B, int ldb, int64_t sB, double beta, double* C,
+          int ldc, int64_t sC, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {
+    // C = beta * C
+    for (int b = 0; b < batch; ++b) {
+      if (beta == 0.0) {
+        for (int r = 0; r < M; ++r) fill(s, C + b * sC + (int64_t)r * ldc, N, 0.0);
+      } else {
+        for (int r = 0; r < M; ++r)
+          axpby(s, N, 0.0, C + b * sC + (int64_t)r * ldc, beta, C + b * sC + (int64_t)r * ldc);
+      }
+    }
+    return;
+  }
+  // Few output tiles and a long K: split K over workgroups into a scratch
+  // buffer and reduce in a second, deterministic pass.
+  const int64_t tiles = (int64_t)cdiv(N, BN) * cdiv(M, BM) * batch;
+  int nsplit = 1;
+  if (g_splitk_buf && tiles < 128 && K >= 4 * BK * 8) {
+    nsplit = (int)std::min<int64_t>({(int64_t)cdiv(K, BK * 8), 256 / tiles + 1, 64});
+    while (nsplit > 1 && (size_t)nsplit * batch * M * N > g_splitk_cap) --nsplit;
+    if ((int64_t)nsplit * batch > 65535) nsplit = 1;
+  }
+  int kchunk = K;
+  if (nsplit > 1) {
+    kchunk = cdiv(cdiv(K, nsplit), BK) * BK;
+    nsplit = cdiv(K, kchunk);
+  }
+  double* out = nsplit > 1 ? g_splitk_buf : C;
+  dim3 grid(cdiv(N, BN), cdiv(M, BM), batch * nsplit);
+  TT_REQUIRE(grid.y <= 65535 && grid.z <= 65535, "gemm grid too large");
+  ++g_launches;
+  if (!ta && !tb)
+    gemm_kernel<false, false><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
+  else if (ta && !tb)
+    gemm_kernel<true, false><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
+  else if (!ta && tb)
+    gemm_kernel<false, true><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
+  else
+    gemm_kernel<true, true><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
+  TT_HIP(hipGetLastError());
+  if (nsplit > 1) {
+    ++g_launches;
+    splitk_reduce_kernel<<<grid_for((int64_t)M * N * batch, 256), 256, 0, s>>>(
+        g_splitk_buf, nsplit, batch, M, N, alpha, beta, C, ldc, sC);
+    TT_HIP(hipGetLastError());
+  }
+}
+
+void transpose(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst,
+               int ldd) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid(cdiv(cols, 32), cdiv(rows, 32));
+  TT_REQUIRE(grid.y <= 65535, "transpose grid too large");
+  ++g_launches;
+  transpose_kernel<<<grid, 256, 0, s>>>(src, rows, cols, lds, dst, ldd);
+  TT_HIP(hipGetLastError());
+}
+
+void copy2d(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst, int ldd) {
+  if (rows <= 0 || cols <= 0) return;
+  ++g_launches;
+  copy2d_kernel<<<grid_for((int64_t)rows * cols, 256), 256, 0, s>>>(src, rows, cols, lds, dst, ldd);
+  TT_HIP(hipGetLastError());
+}
+
+void copy(hipStream_t s, const double* src, double* dst, int64_t n) {
+  if (n <= 0 || src == dst) return;
+  ++g_launches;
+  TT_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+void fill(hipStream_t s, double* dst, int64_t n, double v) {
+  if (n <= 0) return;
+  ++g_launches;
+  fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(dst, n, v);
+  TT_HIP(hipGetLastError());
+}
+
+void axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y) {
+  if (n <= 0) return;
+  ++g_launches;
+  axpby_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, a, x, b, nullptr, y);
+  TT_HIP(hipGetLastError());
+}
+
+void axpby_div(hipStream_t s, int64_t n, double a, const double* x, double b, const double* c,
+               double* y) {
+  if (n <= 0) return;
+  ++g_launches;
+  axpby_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, a, x, b, c, y);
+  TT_HIP(hipGetLastError());
+}
+
+void sumsq(hipStream_t s, const double* x, int64_t n, double* out) {
+  ++g_launches;
+  sumsq_kernel<<<1, 1024, 0, s>>>(x, n, out);
+  TT_HIP(hipGetLastError());
+}
+
+void scale_inv_sqrt(hipStream_t s, double* x, int64_t n, const double* ss) {
+  if (n <= 0) return;
+  ++g_launches;
+  scale_inv_sqrt_kernel<<<grid_for(n, 256), 256, 0, s>>>(x, n, ss);
+  TT_HIP(hipGetLastError());
+}
+
+}  // namespace ttnt

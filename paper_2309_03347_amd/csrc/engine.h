@@ -1,0 +1,102 @@
+// Host-side orchestration of the TT algorithms (rounding, alternating solve,
+// power step) on top of the device kernels.
+#pragma once
+
+#include "common.h"
+
+namespace ttnt {
+
+struct TTv {
+  int d = 0;
+  std::vector<int> n, r, rcap;
+  double* data = nullptr;
+  std::vector<int64_t> off;
+  double* core(int k) const { return data + off[k]; }
+  int64_t size(int k) const { return (int64_t)r[k] * n[k] * r[k + 1]; }
+  int64_t total() const {
+    int64_t t = 0;
+    for (int k = 0; k < d; ++k) t += size(k);
+    return t;
+  }
+};
+
+struct TTm {
+  int d = 0;
+  std::vector<int> m, n, R;
+  const double* data = nullptr;
+  std::vector<int64_t> off;
+  const double* core(int k) const { return data + off[k]; }
+  int64_t size(int k) const { return (int64_t)R[k] * m[k] * n[k] * R[k + 1]; }
+  int64_t total() const {
+    int64_t t = 0;
+    for (int k = 0; k < d; ++k) t += size(k);
+    return t;
+  }
+};
+
+// Bump allocator over device memory; with base == nullptr it only measures.
+struct Bump {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    const size_t at = used;
+    used += (bytes + 255) & ~(size_t)255;
+    if (base && used > cap) throw ArgError{"workspace too small"};
+    return base ? (void*)(base + at) : nullptr;
+  }
+  double* d(size_t count) { return (double*)take(count * sizeof(double)); }
+  int* i(size_t count) { return (int*)take(count * sizeof(int)); }
+};
+
+TTv view(const tt_vec* v);
+TTm view(const tt_mat* m);
+
+// y = A x (exact), y ranks R_k r_k.
+void matvec(hipStream_t s, const TTm& A, const TTv& x, TTv& y);
+// In-place rounding; returns relative discarded norm if rel_err != nullptr (synchronizes).
+void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws);
+size_t round_ws_bytes(const TTv& x);
+// <a, b> into a device scalar `out` (no synchronization).
+void dot_tt(hipStream_t s, const TTv& a, const TTv& b, double* out, Bump& ws);
+size_t dot_ws_bytes(const TTv& a, const TTv& b);
+// Right-orthogonalize cores 1..d-1 (R->L LQ sweep).
+void orth_right(hipStream_t s, TTv& x, Bump& ws);
+
+// Local operator application y = alpha * (PhiL (x) A (x) PhiR) v + beta * y.
+struct LocalOp {
+  const double* phiL;  // [ra][RL][rb]
+  int ra, RL, rb;
+  const double* Ap;    // permuted core [(i, RR), (RL, j)]
+  const double* A;     // natural core [RL][m][n][RR]
+  int m, n, RR;
+  const double* phiR;  // [rc][RR][rd]
+  int rc, rd;
+  bool diag = false;   // core is diagonal in the mode (A[b, i, j, b'] = 0 for i != j)
+};
+void local_apply(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
+                 double beta, double* T1, double* T2);
+
+struct LocalSolveOpts {
+  int method = 0;          // 0 auto, 1 dense LU, 2 GMRES
+  double tol = 1e-10;      // relative residual target
+  double eta = 0.0;        // GMRES also stops at ||r|| <= eta * ||r_0|| (0: off)
+  int max_iter = 400;
+  int restart = 60;
+  int direct_max = 256;    // auto: dense LU up to this many unknowns
+  int block_max = 1024;    // auto: mode-diagonal cores solved as n blocks up to this size
+};
+struct LocalSolveResult {
+  int iterations = 0;
+  int method = 0;
+  double rel_res = 0.0;
+  bool converged = true;
+};
+// Scratch for a local solve of N unknowns (LU and/or GMRES).
+size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o);
+// Solve (PhiL (x) A (x) PhiR) x = f; x holds the initial guess.  `final_res`
+// requests the final residual (one extra apply and a synchronization).
+LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, double* x,
+                             const LocalSolveOpts& o, Bump& ws, bool final_res);
+
+}  // namespace ttnt

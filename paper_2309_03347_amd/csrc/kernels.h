@@ -1,0 +1,63 @@
+// Internal host-side launchers (all enqueue on `s`; none synchronize).
+#pragma once
+
+#include "common.h"
+
+namespace ttnt {
+
+// Launch counter (diagnostic: kernels issued since last reset).
+extern thread_local int64_t g_launches;
+// Scratch for split-K partial products (set by the caller that owns it; null
+// disables the split).  Capacity in doubles.
+extern thread_local double* g_splitk_buf;
+extern thread_local size_t g_splitk_cap;
+
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major, op = transpose if flag.
+// op(A) is M x K, op(B) is K x N.
+void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+          int lda, int64_t sA, const double* B, int ldb, int64_t sB, double beta, double* C,
+          int ldc, int64_t sC, int batch = 1);
+
+// dst[j][i] = src[i][j] for an rows x cols source (row-major, leading dims given).
+void transpose(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst,
+               int ldd);
+// dst[i][j] = src[i][j] (rows x cols).
+void copy2d(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst, int ldd);
+void copy(hipStream_t s, const double* src, double* dst, int64_t n);
+void fill(hipStream_t s, double* dst, int64_t n, double v);
+// y = a * x + b * y
+void axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y);
+// y = a * x + (b / *c) * y   (c device scalar; used for 1/k scaling)
+void axpby_div(hipStream_t s, int64_t n, double a, const double* x, double b, const double* c,
+               double* y);
+// out = sum x^2 (device scalar), single launch.
+void sumsq(hipStream_t s, const double* x, int64_t n, double* out);
+// x *= 1/sqrt(*ss)  (ss device scalar holding a sum of squares)
+void scale_inv_sqrt(hipStream_t s, double* x, int64_t n, const double* ss);
+
+// ---- dense factorizations (one workgroup each) ----
+// Householder QR of A (m x n, lda), overwritten.  Q (m x k, ldq) and R (k x n, ldr),
+// k = min(m, n), with diag(R) >= 0.  A is destroyed.
+void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R, int ldr,
+        double* tau);
+// One-sided Jacobi SVD of G (m x n, m >= n), destroyed.  U (m x n), S (n), V (n x n)
+// row-major, singular values descending; each column of U has its largest-magnitude
+// entry positive (V flipped to match).
+void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
+         double* V, int ldv, double* work);
+size_t svd_work_doubles(int m, int n);
+// Truncation rank: smallest r with sqrt(sum_{i>=r} S_i^2) <= delta, where
+// delta = tol * sqrt(*normsq) / sqrt(dm1) (or tol * ||S|| when normsq == NULL);
+// r capped to [1, rmax]; writes rank[0] (device int), rank[1] = 1 if rmax bound, and adds the discarded
+// sum of squares to *discard (device, may be NULL).
+void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,
+                const double* normsq, int rmax, int* rank, double* discard);
+// Dense LU with partial pivoting of A (N x N, lda; destroyed) and solve A x = b in place.
+// batch > 1: matrices at A + i*N*lda and right-hand sides at b + i*N, one workgroup each.
+void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch = 1);
+
+// ---- TT kernels ----
+void tt_core_matvec(hipStream_t s, const double* A, int R0, int m, int n, int R1,
+                    const double* X, int r0, int r1, double* Y);
+
+}  // namespace ttnt

@@ -1,0 +1,63 @@
+// Power-iteration solver state (one instance per tt_solver handle).
+#pragma once
+
+#include "engine.h"
+
+namespace ttnt {
+
+struct NumericError {};
+
+struct StepStats {
+  int local_iters = 0;
+  bool cap_hit = false;
+};
+
+struct Solver {
+  // device scalars (offsets into `scal`)
+  enum { KVAL = 0, DEN = 1, NUM = 2, NRM2 = 3, KINFO = 4 };
+
+  int d = 0;
+  std::vector<int> n;
+  double tol = 1e-8;
+  int rmax = 32, kick = 4, max_sweeps = 10, rhs_mode = 0, rhs_rmax = 1 << 30;
+  LocalSolveOpts lso;
+  double k_host = 1.0;
+  double stall = 0.5;          // stop sweeping when the residual falls by less than this
+  std::vector<char> Hdiag;
+  int64_t last_launches = 0;
+
+  void* mem = nullptr;
+  size_t mem_bytes = 0;
+
+  TTm H, SF, Id, Ak;
+  double *Hc = nullptr, *SFc = nullptr, *F0 = nullptr, *A0 = nullptr, *Ic = nullptr;
+  std::vector<double*> ApH, ApA, ApI;
+  TTv cF, psi, X, Z, B;
+  std::vector<int> capPsi, capX, zr, capB, capV, capCF, RH, Rop;
+  std::vector<double*> LXH, RXH, LXA, RXA, LZH, RZH, LZA, RZA;
+  double *T1 = nullptr, *T2 = nullptr, *fvec = nullptr, *xloc = nullptr, *yvec = nullptr;
+  double *crz = nullptr, *zc = nullptr, *U2 = nullptr, *U2w = nullptr, *Lft = nullptr;
+  double *RtT = nullptr, *Sv = nullptr, *Rb = nullptr, *tau = nullptr, *tmp = nullptr;
+  double* svdw = nullptr;
+  size_t svd_cap = 0;
+  double* lsw = nullptr;
+  size_t ls_cap = 0;
+  char* rw = nullptr;
+  size_t rw_cap = 0;
+  static constexpr size_t kSplitK = (size_t)1 << 21;   // split-K partials (doubles)
+  double* splitk = nullptr;
+  double *scal = nullptr, *resarr = nullptr;
+  int* irank = nullptr;
+
+  ~Solver();
+  void create(const tt_problem* p, const tt_solver_opts* o);
+  void step(hipStream_t s, tt_step_info* info);
+
+ private:
+  void plan(Bump& b);
+  void sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
+                  const std::vector<double*>& ApOp, StepStats& st);
+};
+
+
+}  // namespace ttnt

@@ -1,0 +1,552 @@
+// Power-iteration solver: AMEn solve of H psi+ = (S + F/k) psi, rounding,
+// eigenvalue update (eq. TT_k_eff_fixed_points).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "engine.h"
+#include "kernels.h"
+#include "solver.h"
+#include "ttk.h"
+
+namespace ttnt {
+namespace {
+
+int64_t sat_mul(int64_t a, int64_t b) {
+  const int64_t lim = (int64_t)1 << 40;
+  const int64_t p = a * b;
+  return p > lim ? lim : p;
+}
+
+// Left interface at bond k+1 from bond k:
+// out[a2, b1, c2] = sum PhiL[a, b, c] Y[a, i, a2] A[b, i, j, b1] X[c, j, c2]
+void iface_left(hipStream_t s, const double* phiL, const double* Y, int ry0, int ry1,
+                const double* Ap, int RL, int m, int n, int RR, const double* X, int rx0,
+                int rx1, double* out, double* T1, double* T2) {
+  gemm(s, false, false, ry0 * RL, n * rx1, rx0, 1.0, phiL, rx0, 0, X, n * rx1, 0, 0.0, T1,
+       n * rx1, 0);
+  gemm(s, false, false, m * RR, rx1, RL * n, 1.0, Ap, RL * n, 0, T1, rx1, (int64_t)RL * n * rx1,
+       0.0, T2, rx1, (int64_t)m * RR * rx1, ry0);
+  gemm(s, true, false, ry1, RR * rx1, ry0 * m, 1.0, Y, ry1, 0, T2, RR * rx1, 0, 0.0, out,
+       RR * rx1, 0);
+}
+
+// Right interface at bond k from bond k+1:
+// out[a, b, c] = sum Y[a, i, a2] A[b, i, j, b1] X[c, j, c2] PhiR[a2, b1, c2]
+void iface_right(hipStream_t s, const double* phiR, const double* Y, int ry0, int ry1,
+                 const double* Ap, int RL, int m, int n, int RR, const double* X, int rx0,
+                 int rx1, double* out, double* T1, double* T2) {
+  gemm(s, false, false, ry0 * m, RR * rx1, ry1, 1.0, Y, ry1, 0, phiR, RR * rx1, 0, 0.0, T1,
+       RR * rx1, 0);
+  gemm(s, true, false, RL * n, rx1, m * RR, 1.0, Ap, RL * n, 0, T1, rx1, (int64_t)m * RR * rx1,
+       0.0, T2, rx1, (int64_t)RL * n * rx1, ry0);
+  gemm(s, false, true, ry0 * RL, rx0, n * rx1, 1.0, T2, n * rx1, 0, X, n * rx1, 0, 0.0, out,
+       rx0, 0);
+}
+
+uint64_t lcg(uint64_t& st) {
+  st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+  return st >> 11;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Planning: the same routine sizes (dry run) and carves the device memory.
+// ---------------------------------------------------------------------------
+void Solver::plan(Bump& b) {
+  const int dd = d;
+  // operators: H, SF (with core 0 replaced by A0), identity, F0, permuted cores
+  Hc = b.d(H.total());
+  SFc = b.d(SF.total());
+  F0 = b.d(SF.size(0));
+  A0 = b.d(SF.size(0));
+  Ic = b.d(Id.total());
+  ApH.assign(dd, nullptr);
+  ApA.assign(dd, nullptr);
+  ApI.assign(dd, nullptr);
+  for (int k = 0; k < dd; ++k) {
+    ApH[k] = b.d(H.size(k));
+    ApA[k] = b.d(SF.size(k));
+    ApI[k] = b.d(Id.size(k));
+  }
+  // TT vectors
+  auto carve_vec = [&](TTv& v, const std::vector<int>& cap) {
+    v.d = dd;
+    v.n = n;
+    v.rcap = cap;
+    if ((int)v.r.size() != dd + 1) v.r.assign(dd + 1, 1);
+    v.off.assign(dd, 0);
+    int64_t tot = 0;
+    for (int k = 0; k < dd; ++k) {
+      v.off[k] = tot;
+      tot += (int64_t)cap[k] * n[k] * cap[k + 1];
+    }
+    v.data = b.d(tot + 8);
+  };
+  carve_vec(psi, capPsi);
+  carve_vec(X, capX);
+  carve_vec(Z, zr);
+  carve_vec(cF, capCF);
+  if (rhs_mode == 1) carve_vec(B, capB);
+  // interfaces
+  auto carve_if = [&](std::vector<double*>& L, std::vector<double*>& R,
+                      const std::vector<int>& bra, const std::vector<int>& op,
+                      const std::vector<int>& ket) {
+    L.assign(dd + 1, nullptr);
+    R.assign(dd + 1, nullptr);
+    for (int k = 0; k <= dd; ++k) {
+      const int64_t sz = (int64_t)bra[k] * op[k] * ket[k] + 1;
+      L[k] = b.d(sz);
+      R[k] = b.d(sz);
+    }
+  };
+  carve_if(LXH, RXH, capX, RH, capX);
+  carve_if(LXA, RXA, capX, Rop, capV);
+  carve_if(LZH, RZH, zr, RH, capX);
+  carve_if(LZA, RZA, zr, Rop, capV);
+  // scratch
+  int64_t tmax = 16, coreX = 16, dimX = 16;
+  for (int k = 0; k < dd; ++k) {
+    const int64_t lcap = std::max(capX[k], zr[k]);
+    const int64_t rcap = std::max({capX[k + 1], capV[k + 1], zr[k + 1]});
+    const int64_t rop = std::max({RH[k], RH[k + 1], Rop[k], Rop[k + 1]});
+    tmax = std::max(tmax, lcap * n[k] * rcap * rop);
+    coreX = std::max(coreX, (int64_t)capX[k] * n[k] * capX[k + 1]);
+    dimX = std::max(dimX, (int64_t)std::max(capX[k] * n[k], capX[k + 1] + kick));
+  }
+  T1 = b.d(tmax);
+  T2 = b.d(tmax);
+  fvec = b.d(coreX);
+  xloc = b.d(coreX);
+  yvec = b.d(coreX);
+  crz = b.d(coreX + dimX * (kick + 1));
+  zc = b.d(coreX + dimX * (kick + 1));
+  U2 = b.d(coreX + dimX * (kick + 1));
+  U2w = b.d(coreX + dimX * (kick + 1));
+  Lft = b.d(coreX + dimX);
+  RtT = b.d(coreX + dimX);
+  Sv = b.d(dimX + 8);
+  Rb = b.d(coreX + dimX * (kick + 1));
+  tau = b.d(dimX + kick + 8);
+  tmp = b.d(coreX + dimX * (kick + 1));
+  int64_t svdn = 16;
+  for (int k = 0; k < dd; ++k) {
+    const int64_t rows = (int64_t)capX[k] * n[k], cols = capX[k + 1];
+    const int64_t M = std::max(rows, cols), p = std::min(rows, cols);
+    svdn = std::max(svdn, (int64_t)(2 * M * p + p * p + svd_work_doubles((int)M, (int)p)));
+  }
+  svdw = b.d(svdn + 512);
+  svd_cap = (size_t)(svdn + 512) * sizeof(double);
+  // local solve scratch: the larger of the LU and GMRES needs at capacity
+  int64_t lsn = 16;
+  for (int k = 0; k < dd; ++k) {
+    LocalOp op{};
+    op.ra = op.rb = capX[k];
+    op.rc = op.rd = capX[k + 1];
+    op.RL = RH[k];
+    op.RR = RH[k + 1];
+    op.m = op.n = n[k];
+    LocalSolveOpts o2 = lso;
+    const int64_t N = (int64_t)op.ra * op.n * op.rc;
+    o2.method = 2;
+    lsn = std::max(lsn, (int64_t)local_solve_ws_doubles(op, o2));
+    if (Hdiag[k]) {
+      const int64_t Bm = std::min<int64_t>((int64_t)op.ra * op.rc, lso.block_max);
+      const int64_t t = (int64_t)op.ra * std::max(op.RL, op.RR) * n[k] * op.rd;
+      lsn = std::max(lsn, 2 * t + (int64_t)op.RL * n[k] * op.RR +
+                              (int64_t)op.RL * n[k] * op.rc * op.rc + (int64_t)n[k] * Bm * Bm + N +
+                              4096);
+    }
+    if (lso.method != 2) {
+      // largest dense system that can occur at this core
+      o2.method = 1;
+      LocalOp lo = op;
+      if (N > lso.direct_max && lso.method == 0) {
+        // LU only for N <= direct_max: bound rc by direct_max / (ra n) and ra by direct_max / n
+        const int64_t dm = lso.direct_max;
+        lo.ra = lo.rb = (int)std::min<int64_t>(op.ra, std::max<int64_t>(1, dm / n[k]));
+        lo.rc = lo.rd = (int)std::min<int64_t>(op.rc, std::max<int64_t>(1, dm / n[k]));
+        const int64_t Nl = std::min<int64_t>(N, dm);
+        int64_t need = (int64_t)local_solve_ws_doubles(lo, o2);
+        need = std::max(need, Nl * Nl + (int64_t)op.RL * n[k] * n[k] * lo.rc * lo.rc +
+                                  (int64_t)lo.ra * op.RL * n[k] * lo.rc * 2 + Nl + 4096);
+        lsn = std::max(lsn, need);
+      } else {
+        lsn = std::max(lsn, (int64_t)local_solve_ws_doubles(op, o2));
+      }
+    }
+  }
+  lsw = b.d(lsn + 64);
+  ls_cap = (size_t)(lsn + 64) * sizeof(double);
+  // rounding / dot / orthogonalization scratch
+  {
+    TTv t;
+    t.d = dd;
+    t.n = n;
+    t.r = capX;
+    size_t need = round_ws_bytes(t);
+    if (rhs_mode == 1) {
+      TTv tb;
+      tb.d = dd;
+      tb.n = n;
+      tb.r = capB;
+      need = std::max(need, round_ws_bytes(tb));
+    }
+    TTv tz;
+    tz.d = dd;
+    tz.n = n;
+    tz.r = capCF;
+    need = std::max(need, dot_ws_bytes(tz, t));
+    rw = (char*)b.take(need + 4096);
+    rw_cap = need + 4096;
+  }
+  splitk = b.d(kSplitK);
+  scal = b.d(64);
+  resarr = b.d(dd + 8);
+  irank = b.i(16);
+}
+
+Solver::~Solver() {
+  if (mem) (void)hipFree(mem);
+}
+
+void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
+  TT_REQUIRE(p && o, "null problem or options");
+  H = view(&p->H);
+  SF = view(&p->SF);
+  const TTv cf_in = view(&p->cF);
+  const TTv psi_in = view(&p->psi0);
+  d = H.d;
+  TT_REQUIRE(d >= 1 && SF.d == d && cf_in.d == d && psi_in.d == d, "core counts differ");
+  n = H.n;
+  for (int k = 0; k < d; ++k) {
+    TT_REQUIRE(H.m[k] == n[k] && SF.m[k] == n[k] && SF.n[k] == n[k], "operators must be square");
+    TT_REQUIRE(cf_in.n[k] == n[k] && psi_in.n[k] == n[k], "vector modes differ");
+  }
+  TT_REQUIRE(H.R[0] == 1 && H.R[d] == 1 && SF.R[0] == 1 && SF.R[d] == 1, "boundary ranks");
+  TT_REQUIRE(p->F_core0 != nullptr, "F_core0 is required");
+  TT_REQUIRE(p->k0 > 0.0, "k0 must be positive");
+  tol = o->tol;
+  rmax = o->rmax;
+  kick = o->kick;
+  max_sweeps = o->max_sweeps;
+  rhs_mode = o->rhs_mode;
+  rhs_rmax = o->rhs_rmax > 0 ? o->rhs_rmax : (1 << 30);
+  TT_REQUIRE(tol > 0.0 && rmax >= 1 && kick >= 1 && max_sweeps >= 1, "bad solver options");
+  TT_REQUIRE(rhs_mode == 0 || rhs_mode == 1, "rhs_mode must be 0 or 1");
+  lso.method = 0;
+  lso.tol = o->local_tol > 0.0 ? o->local_tol : tol / std::sqrt((double)d);
+  lso.max_iter = o->gmres_max_iter > 0 ? o->gmres_max_iter : 1000;
+  lso.restart = o->gmres_restart > 0 ? o->gmres_restart : 80;
+  lso.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
+  lso.eta = 0.0;
+  // identity operator (explicit mode right-hand side)
+  Id.d = d;
+  Id.m = n;
+  Id.n = n;
+  Id.R.assign(d + 1, 1);
+  // capacities
+  std::vector<int64_t> pl(d + 1, 1), pr(d + 1, 1);
+  for (int k = 0; k < d; ++k) pl[k + 1] = sat_mul(pl[k], n[k]);
+  for (int k = d - 1; k >= 0; --k) pr[k] = sat_mul(pr[k + 1], n[k]);
+  capPsi.assign(d + 1, 1);
+  capX.assign(d + 1, 1);
+  zr.assign(d + 1, 1);
+  capB.assign(d + 1, 1);
+  capV.assign(d + 1, 1);
+  capCF = cf_in.r;
+  RH = H.R;
+  for (int k = 1; k < d; ++k) {
+    capPsi[k] = (int)std::min<int64_t>({(int64_t)rmax, pl[k], pr[k]});
+    capPsi[k] = std::max(capPsi[k], psi_in.r[k]);
+    capX[k] = (int)std::min<int64_t>((int64_t)std::max(rmax, psi_in.r[k]) + kick, pl[k]);
+    zr[k] = (int)std::min<int64_t>({(int64_t)kick, pl[k], pr[k]});
+    capB[k] = SF.R[k] * capPsi[k];
+    capV[k] = rhs_mode == 0 ? capPsi[k]
+                            : (int)std::min<int64_t>({(int64_t)rhs_rmax, pl[k], pr[k],
+                                                      (int64_t)capB[k]});
+  }
+  Rop = rhs_mode == 0 ? SF.R : Id.R;
+  // mode-diagonal cores of H (the transport operator does not couple groups
+  // or directions): their local systems split into independent blocks
+  Hdiag.assign(d, false);
+  for (int k = 0; k < d; ++k) {
+    if (n[k] <= 2) continue;
+    std::vector<double> h(H.size(k));
+    TT_HIP(hipMemcpy(h.data(), H.core(k), h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    bool diag = true;
+    for (int b = 0; b < H.R[k] && diag; ++b)
+      for (int i = 0; i < n[k] && diag; ++i)
+        for (int j = 0; j < n[k] && diag; ++j)
+          if (i != j)
+            for (int c = 0; c < H.R[k + 1]; ++c)
+              if (h[(((int64_t)b * n[k] + i) * n[k] + j) * H.R[k + 1] + c] != 0.0) {
+                diag = false;
+                break;
+              }
+    Hdiag[k] = diag;
+  }
+  // dry run, allocate, carve
+  Bump dry;
+  plan(dry);
+  mem_bytes = dry.used + 4096;
+  TT_HIP(hipMalloc(&mem, mem_bytes));
+  Bump real;
+  real.base = (char*)mem;
+  real.cap = mem_bytes;
+  plan(real);
+  hipStream_t s = nullptr;
+  // operator copies
+  TTm Hsrc = H, SFsrc = SF;
+  auto copy_mat = [&](const TTm& src, double* dst, TTm& out) {
+    int64_t off = 0;
+    out = src;
+    for (int k = 0; k < d; ++k) {
+      copy(s, src.core(k), dst + off, src.size(k));
+      out.off[k] = off;
+      off += src.size(k);
+    }
+    out.data = dst;
+  };
+  copy_mat(Hsrc, Hc, H);
+  copy_mat(SFsrc, SFc, SF);
+  copy(s, p->F_core0, F0, SF.size(0));
+  {
+    std::vector<double> hid;
+    int64_t off = 0;
+    Id.off.assign(d, 0);
+    for (int k = 0; k < d; ++k) {
+      Id.off[k] = off;
+      for (int i = 0; i < n[k]; ++i)
+        for (int j = 0; j < n[k]; ++j) hid.push_back(i == j ? 1.0 : 0.0);
+      off += (int64_t)n[k] * n[k];
+    }
+    TT_HIP(hipMemcpy(Ic, hid.data(), hid.size() * sizeof(double), hipMemcpyHostToDevice));
+    Id.data = Ic;
+  }
+  for (int k = 0; k < d; ++k) {
+    permute_op(s, H.core(k), H.R[k], n[k], n[k], H.R[k + 1], ApH[k]);
+    permute_op(s, SF.core(k), SF.R[k], n[k], n[k], SF.R[k + 1], ApA[k]);
+    permute_op(s, Id.core(k), 1, n[k], n[k], 1, ApI[k]);
+  }
+  // A(k) view: core 0 -> A0, others -> SF
+  Ak = SF;
+  Ak.off[0] = A0 - SF.data;
+
+  // vectors
+  for (int k = 0; k < d; ++k) copy(s, cf_in.core(k), cF.core(k), cf_in.size(k));
+  cF.r = cf_in.r;
+  for (int k = 0; k < d; ++k) copy(s, psi_in.core(k), psi.core(k), psi_in.size(k));
+  psi.r = psi_in.r;
+  // random Z (fixed seed), unit interface at the chain ends
+  {
+    uint64_t st = 0x9E3779B97F4A7C15ULL;
+    for (int k = 0; k < d; ++k) {
+      const int64_t sz = (int64_t)zr[k] * n[k] * zr[k + 1];
+      std::vector<double> h(sz);
+      for (auto& v : h) v = ((double)(lcg(st) & 0xFFFFFF) / (double)0xFFFFFF) - 0.5;
+      TT_HIP(hipMemcpy(Z.core(k), h.data(), sz * sizeof(double), hipMemcpyHostToDevice));
+    }
+    Z.r = zr;
+    for (auto* v : {&LXH, &LXA, &LZH, &LZA}) fill(s, (*v)[0], 1, 1.0);
+    for (auto* v : {&RXH, &RXA, &RZH, &RZA}) fill(s, (*v)[d], 1, 1.0);
+  }
+  // k and the normalized start vector
+  TT_HIP(hipMemcpy(scal + KVAL, &p->k0, sizeof(double), hipMemcpyHostToDevice));
+  k_host = p->k0;
+  {
+    Bump w;
+    w.base = rw;
+    w.cap = rw_cap;
+    orth_right(s, psi, w);
+    sumsq(s, psi.core(0), psi.size(0), scal + NRM2);
+    scale_inv_sqrt(s, psi.core(0), psi.size(0), scal + NRM2);
+    w.used = 0;
+    dot_tt(s, cF, psi, scal + DEN, w);
+  }
+  TT_HIP(hipDeviceSynchronize());
+}
+
+void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
+                        const std::vector<double*>& ApOp, StepStats& st) {
+  const int rk = X.r[k], rk1 = X.r[k + 1], nk = n[k];
+  const int vk = V.r[k], vk1 = V.r[k + 1];
+  LocalOp xh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RXH[k + 1], rk1, rk1,
+             (bool)Hdiag[k]};
+  LocalOp xa{LXA[k], rk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RXA[k + 1], rk1, vk1};
+  const int64_t N = (int64_t)rk * nk * rk1;
+  local_apply(s, xa, V.core(k), fvec, 1.0, 0.0, T1, T2);
+  local_apply(s, xh, X.core(k), yvec, 1.0, 0.0, T1, T2);
+  rel_res(s, yvec, fvec, N, resarr + k);
+  copy(s, X.core(k), xloc, N);
+  Bump lw;
+  lw.base = (char*)lsw;
+  lw.cap = ls_cap;
+  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lso, lw, false);
+  st.local_iters += lr.iterations;
+  if (k == d - 1) {
+    copy(s, xloc, X.core(k), N);
+    return;
+  }
+  // truncated SVD of the solved core, (r_k n_k) x r_{k+1}
+  const int rows = rk * nk, cols = rk1;
+  Bump sw;
+  sw.base = (char*)svdw;
+  sw.cap = svd_cap;
+  const int64_t M = std::max(rows, cols), pp = std::min(rows, cols);
+  double* sG = sw.d(M * pp);
+  double* sU = sw.d(M * pp);
+  double* sV = sw.d(pp * pp);
+  double* sWk = sw.d(svd_work_doubles((int)M, (int)pp));
+  int p;
+  if (rows >= cols) {
+    p = cols;
+    svd(s, xloc, rows, cols, cols, Lft, p, Sv, sV, p, sWk);
+    transpose(s, sV, p, p, p, RtT, cols);
+  } else {
+    p = rows;
+    transpose(s, xloc, rows, cols, cols, sG, rows);
+    svd(s, sG, cols, rows, rows, sU, rows, Sv, Lft, p, sWk);
+    transpose(s, sU, cols, rows, rows, RtT, cols);
+  }
+  trunc_rank(s, Sv, p, tol, (double)d, nullptr, rmax, irank, nullptr);
+  int rr[2] = {0, 0};
+  TT_HIP(hipMemcpyAsync(rr, irank, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  TT_HIP(hipStreamSynchronize(s));
+  const int rt = rr[0];
+  if (rr[1]) st.cap_hit = true;
+  const int kz = Z.r[k + 1];
+  const int w = rt + kz;
+  // U2 = [u | crz]
+  copy2d(s, Lft, rows, rt, p, U2, w);
+  // xtr = u diag(S) v^T  (uses Lft scaled in place)
+  scale_cols(s, Lft, rows, rt, p, Sv);
+  gemm(s, false, false, rows, cols, rt, 1.0, Lft, p, 0, RtT, cols, 0, 0.0, yvec, cols, 0);
+  // enrichment: residual projected with X on the left and Z on the right
+  LocalOp za{LXA[k], rk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RZA[k + 1], kz, vk1};
+  LocalOp zh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RZH[k + 1], kz, rk1};
+  local_apply(s, za, V.core(k), crz, 1.0, 0.0, T1, T2);
+  local_apply(s, zh, yvec, crz, -1.0, 1.0, T1, T2);
+  copy2d(s, crz, rows, kz, kz, U2 + rt, w);
+  const int q = std::min(rows, w);
+  if (q > X.rcap[k + 1]) throw CapacityError{"enriched rank exceeds capacity"};
+  qr(s, U2, rows, w, w, X.core(k), q, Rb, w, tau);
+  // next core: (R[:, :rt] diag(S) v^T) X_{k+1}
+  scale_cols(s, Rb, q, rt, w, Sv);
+  gemm(s, false, false, q, cols, rt, 1.0, Rb, w, 0, RtT, cols, 0, 0.0, U2w, cols, 0);
+  const int n2 = n[k + 1] * X.r[k + 2];
+  gemm(s, false, false, q, n2, cols, 1.0, U2w, cols, 0, X.core(k + 1), n2, 0, 0.0, tmp, n2, 0);
+  copy(s, tmp, X.core(k + 1), (int64_t)q * n2);
+  // Z core update: residual projected with Z on both sides
+  const int zk = Z.r[k];
+  LocalOp zza{LZA[k], zk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RZA[k + 1], kz, vk1};
+  LocalOp zzh{LZH[k], zk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RZH[k + 1], kz, rk1};
+  local_apply(s, zza, V.core(k), zc, 1.0, 0.0, T1, T2);
+  local_apply(s, zzh, yvec, zc, -1.0, 1.0, T1, T2);
+  qr(s, zc, zk * nk, kz, kz, Z.core(k), kz, U2w, kz, tau);
+  X.r[k + 1] = q;
+  // left interfaces at bond k+1
+  iface_left(s, LXH[k], X.core(k), rk, q, ApH[k], RH[k], nk, nk, RH[k + 1], X.core(k), rk, q,
+             LXH[k + 1], T1, T2);
+  iface_left(s, LXA[k], X.core(k), rk, q, ApOp[k], Rop[k], nk, nk, Rop[k + 1], V.core(k), vk,
+             vk1, LXA[k + 1], T1, T2);
+  iface_left(s, LZH[k], Z.core(k), zk, kz, ApH[k], RH[k], nk, nk, RH[k + 1], X.core(k), rk, q,
+             LZH[k + 1], T1, T2);
+  iface_left(s, LZA[k], Z.core(k), zk, kz, ApOp[k], Rop[k], nk, nk, Rop[k + 1], V.core(k), vk,
+             vk1, LZA[k + 1], T1, T2);
+}
+
+void Solver::step(hipStream_t s, tt_step_info* info) {
+  g_launches = 0;
+  struct SplitScope {
+    SplitScope(double* p, size_t c) { g_splitk_buf = p; g_splitk_cap = c; }
+    ~SplitScope() { g_splitk_buf = nullptr; g_splitk_cap = 0; }
+  } split_scope(splitk, kSplitK);
+  StepStats st;
+  // A(k) core 0 = SF_0 + F_0 / k
+  copy(s, F0, A0, SF.size(0));
+  axpby_div(s, SF.size(0), 1.0, SF.core(0), 1.0, scal + KVAL, A0);
+  permute_op(s, A0, SF.R[0], n[0], n[0], SF.R[1], ApA[0]);
+  Bump w;
+  w.base = rw;
+  w.cap = rw_cap;
+  const TTv* V = &psi;
+  const TTm* Aop = &Ak;
+  const std::vector<double*>* ApOp = &ApA;
+  if (rhs_mode == 1) {
+    matvec(s, Ak, psi, B);
+    w.used = 0;
+    round_tt(s, B, tol, rhs_rmax, nullptr, w);
+    V = &B;
+    Aop = &Id;
+    ApOp = &ApI;
+  }
+  // warm start X = psi
+  X.r = psi.r;
+  for (int k = 0; k < d; ++k) copy(s, psi.core(k), X.core(k), psi.size(k));
+  double max_res = 0.0, prev_res = 1e300;
+  int sweeps = 0;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    st.cap_hit = false;
+    w.used = 0;
+    orth_right(s, X, w);
+    w.used = 0;
+    orth_right(s, Z, w);
+    for (int k = d - 1; k >= 1; --k) {
+      iface_right(s, RXH[k + 1], X.core(k), X.r[k], X.r[k + 1], ApH[k], RH[k], n[k], n[k],
+                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RXH[k], T1, T2);
+      iface_right(s, RXA[k + 1], X.core(k), X.r[k], X.r[k + 1], (*ApOp)[k], Rop[k], n[k], n[k],
+                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RXA[k], T1, T2);
+      iface_right(s, RZH[k + 1], Z.core(k), Z.r[k], Z.r[k + 1], ApH[k], RH[k], n[k], n[k],
+                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RZH[k], T1, T2);
+      iface_right(s, RZA[k + 1], Z.core(k), Z.r[k], Z.r[k + 1], (*ApOp)[k], Rop[k], n[k], n[k],
+                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RZA[k], T1, T2);
+    }
+    for (int k = 0; k < d; ++k) sweep_core(s, k, *V, *Aop, *ApOp, st);
+    std::vector<double> res(d);
+    TT_HIP(hipMemcpyAsync(res.data(), resarr, d * sizeof(double), hipMemcpyDeviceToHost, s));
+    TT_HIP(hipStreamSynchronize(s));
+    max_res = 0.0;
+    for (double v : res) max_res = std::max(max_res, v);
+    ++sweeps;
+    if (!(max_res == max_res)) throw NumericError{};
+    if (max_res < tol) break;
+    // stagnation: the rank cap bound and the residual no longer falls
+    if (st.cap_hit && sweeps >= 2 && max_res > stall * prev_res) break;
+    prev_res = max_res;
+  }
+  // compress the solution and update k
+  double trunc = 0.0;
+  w.used = 0;
+  round_tt(s, X, tol, rmax, &trunc, w);
+  w.used = 0;
+  dot_tt(s, cF, X, scal + NUM, w);
+  k_update(s, scal + KVAL, scal + NUM, scal + DEN, scal + KINFO);
+  sumsq(s, X.core(0), X.size(0), scal + NRM2);
+  scale_inv_sqrt(s, X.core(0), X.size(0), scal + NRM2);
+  scale_ratio(s, scal + NUM, scal + NRM2, scal + DEN);
+  psi.r = X.r;
+  for (int k = 0; k < d; ++k) copy(s, X.core(k), psi.core(k), X.size(k));
+  double kinfo[2];
+  TT_HIP(hipMemcpyAsync(kinfo, scal + KINFO, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  TT_HIP(hipStreamSynchronize(s));
+  k_host = kinfo[0];
+  if (info) {
+    info->k = kinfo[0];
+    info->k_prev = kinfo[1];
+    info->dk = std::fabs(kinfo[0] - kinfo[1]);
+    info->max_local_res = max_res;
+    info->trunc_err = trunc;
+    info->sweeps = sweeps;
+    int mr = 0;
+    for (int v : psi.r) mr = std::max(mr, v);
+    info->max_rank = mr;
+    info->local_iters = st.local_iters;
+    info->status = max_res < tol ? TT_OK : TT_E_NOCONV;
+  }
+  if (!(kinfo[0] == kinfo[0]) || !std::isfinite(kinfo[0])) throw NumericError{};
+  last_launches = g_launches;
+}
+
+}  // namespace ttnt

@@ -1,0 +1,374 @@
+// Tensor-train kernels: core matvec, operator-core permutation, dense local
+// matrix, Krylov (Arnoldi) step, small vector helpers.
+#include "kernels.h"
+#include "ttk.h"
+
+namespace ttnt {
+namespace {
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// Y[(b*r0 + a), i, (b'*r1 + a')] = sum_j A[b, i, j, b'] X[a, j, a']
+__global__ __launch_bounds__(256) void core_matvec_kernel(const double* __restrict__ A, int R0,
+                                                          int m, int n, int R1,
+                                                          const double* __restrict__ X, int r0,
+                                                          int r1, double* __restrict__ Y) {
+  const int64_t C = (int64_t)R1 * r1;
+  const int64_t total = (int64_t)R0 * r0 * m * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = e % C;
+    const int64_t t = e / C;
+    const int i = (int)(t % m);
+    const int64_t row = t / m;
+    const int b = (int)(row / r0), a = (int)(row % r0);
+    const int bp = (int)(col / r1), ap = (int)(col % r1);
+    const double* Ab = A + (((int64_t)b * m + i) * n) * R1 + bp;
+    const double* Xa = X + ((int64_t)a * n) * r1 + ap;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc = fma(Ab[(int64_t)j * R1], Xa[(int64_t)j * r1], acc);
+    Y[e] = acc;
+  }
+}
+
+// Ap[(i*RR + b'), (b*n + j)] = A[b, i, j, b']
+__global__ void permute_op_kernel(const double* __restrict__ A, int RL, int m, int n, int RR,
+                                  double* __restrict__ Ap) {
+  const int64_t total = (int64_t)RL * m * n * RR;
+  const int64_t cols = (int64_t)RL * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / cols, col = e % cols;
+    const int i = (int)(row / RR), bp = (int)(row % RR);
+    const int b = (int)(col / n), j = (int)(col % n);
+    Ap[e] = A[(((int64_t)b * m + i) * n + j) * RR + bp];
+  }
+}
+
+// M[(a,i,c), (a2,j,c2)] = sum_b PhiL[a, b, a2] P[(b,i,j), c, c2]
+__global__ void local_matrix_kernel(const double* __restrict__ phiL, int ra, int RL,
+                                    const double* __restrict__ P, int m, int n, int rc,
+                                    double* __restrict__ M) {
+  const int64_t N = (int64_t)ra * n * rc;
+  const int64_t total = (int64_t)ra * m * rc * N;
+  const int64_t rc2 = (int64_t)rc * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / N, col = e % N;
+    const int c = (int)(row % rc);
+    const int i = (int)((row / rc) % m);
+    const int a = (int)(row / ((int64_t)rc * m));
+    const int c2 = (int)(col % rc);
+    const int j = (int)((col / rc) % n);
+    const int a2 = (int)(col / ((int64_t)rc * n));
+    double acc = 0.0;
+    for (int b = 0; b < RL; ++b)
+      acc = fma(phiL[((int64_t)a * RL + b) * ra + a2],
+                P[(((int64_t)b * m + i) * n + j) * rc2 + (int64_t)c * rc + c2], acc);
+    M[e] = acc;
+  }
+}
+
+// Diagonal of an operator core: Hd[b][i][b'] = A[b, i, i, b']
+__global__ void op_diag_kernel(const double* __restrict__ A, int RL, int n, int RR,
+                               double* __restrict__ Hd) {
+  const int64_t total = (int64_t)RL * n * RR;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int bp = (int)(e % RR);
+    const int i = (int)((e / RR) % n);
+    const int b = (int)(e / ((int64_t)RR * n));
+    Hd[e] = A[(((int64_t)b * n + i) * n + i) * RR + bp];
+  }
+}
+
+// Block-diagonal local matrices of a mode-diagonal core:
+// M[i][(a,c), (a2,c2)] = sum_b PhiL[a, b, a2] P[(b,i)][c][c2]
+__global__ void local_matrix_diag_kernel(const double* __restrict__ phiL, int ra, int RL,
+                                         const double* __restrict__ P, int n, int rc,
+                                         double* __restrict__ M) {
+  const int64_t B = (int64_t)ra * rc;
+  const int64_t total = (int64_t)n * B * B;
+  const int64_t rc2 = (int64_t)rc * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = e % B, row = (e / B) % B;
+    const int i = (int)(e / (B * B));
+    const int a = (int)(row / rc), c = (int)(row % rc);
+    const int a2 = (int)(col / rc), c2 = (int)(col % rc);
+    double acc = 0.0;
+    for (int b = 0; b < RL; ++b)
+      acc = fma(phiL[((int64_t)a * RL + b) * ra + a2],
+                P[((int64_t)b * n + i) * rc2 + (int64_t)c * rc + c2], acc);
+    M[e] = acc;
+  }
+}
+
+// [a][i][c] <-> [i][a][c]
+__global__ void swap_mode_kernel(const double* __restrict__ src, int ra, int n, int rc,
+                                 double* __restrict__ dst, int to_blocks) {
+  const int64_t total = (int64_t)ra * n * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % rc);
+    const int i = (int)((e / rc) % n);
+    const int a = (int)(e / ((int64_t)rc * n));
+    const int64_t blk = ((int64_t)i * ra + a) * rc + c;
+    if (to_blocks) dst[blk] = src[e]; else dst[e] = src[blk];
+  }
+}
+
+__global__ void scale_cols_kernel(double* __restrict__ X, int rows, int cols, int ld,
+                                  const double* __restrict__ s) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    X[(int64_t)r * ld + c] *= s[c];
+  }
+}
+
+// GMRES Arnoldi step (one workgroup): V rows are Krylov vectors of length N.
+// On entry V[j+1] holds w = A V[j].  CGS2 against V[0..j]; H column j
+// (stored Hc[j*(ldh) + i]); Givens update of g; writes |g[j+1]| to *res.
+__global__ __launch_bounds__(1024) void arnoldi_kernel(double* __restrict__ V, int64_t N, int j,
+                                                       double* __restrict__ Hc, int ldh,
+                                                       double* __restrict__ cs,
+                                                       double* __restrict__ sn,
+                                                       double* __restrict__ g,
+                                                       double* __restrict__ res) {
+  __shared__ double red[16];
+  __shared__ double h[1024];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+  double* w = V + (int64_t)(j + 1) * N;
+  double* hcol = Hc + (int64_t)j * ldh;
+  for (int i = tid; i <= j + 1; i += nt) h[i] = 0.0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = wid; i <= j; i += nw) {
+      const double* vi = V + (int64_t)i * N;
+      double acc = 0.0;
+      for (int64_t e = lane; e < N; e += 64) acc = fma(vi[e], w[e], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) h[512 + i] = acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < N; e += nt) {
+      double acc = w[e];
+      for (int i = 0; i <= j; ++i) acc -= h[512 + i] * V[(int64_t)i * N + e];
+      w[e] = acc;
+    }
+    for (int i = tid; i <= j; i += nt) h[i] += h[512 + i];
+    __syncthreads();
+  }
+  double v = 0.0;
+  for (int64_t e = tid; e < N; e += nt) v = fma(w[e], w[e], v);
+  const double nrm = sqrt(block_sum(v, red));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t e = tid; e < N; e += nt) w[e] *= inv;
+  if (tid == 0) {
+    h[j + 1] = nrm;
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+      h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    const double a = h[j], b = h[j + 1];
+    const double rr = sqrt(a * a + b * b);
+    const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    h[j] = rr;
+    h[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    for (int i = 0; i <= j; ++i) hcol[i] = h[i];
+    *res = fabs(g[j + 1]);
+  }
+}
+
+// Solve the k x k upper-triangular least-squares system and update x += V^T y.
+__global__ __launch_bounds__(1024) void gmres_update_kernel(const double* __restrict__ V,
+                                                            int64_t N, int k,
+                                                            const double* __restrict__ Hc,
+                                                            int ldh, const double* __restrict__ g,
+                                                            double* __restrict__ x) {
+  __shared__ double y[1024];
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int c = i + 1; c < k; ++c) acc -= Hc[(int64_t)c * ldh + i] * y[c];
+      const double d = Hc[(int64_t)i * ldh + i];
+      y[i] = d != 0.0 ? acc / d : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < N; e += blockDim.x) {
+    double acc = x[e];
+    for (int i = 0; i < k; ++i) acc = fma(y[i], V[(int64_t)i * N + e], acc);
+    x[e] = acc;
+  }
+}
+
+// r = f - r ; beta = ||r|| ; V0 = r / beta ; g = [beta, 0, ...] ; out[0] = beta, out[1] = ||f||
+__global__ __launch_bounds__(1024) void gmres_start_kernel(const double* __restrict__ f,
+                                                           double* __restrict__ r, int64_t N,
+                                                           double* __restrict__ V0,
+                                                           double* __restrict__ g, int gl,
+                                                           double* __restrict__ out) {
+  __shared__ double red[16];
+  double a = 0.0, b = 0.0;
+  for (int64_t e = threadIdx.x; e < N; e += blockDim.x) {
+    const double t = f[e] - r[e];
+    r[e] = t;
+    a = fma(t, t, a);
+    b = fma(f[e], f[e], b);
+  }
+  const double beta = sqrt(block_sum(a, red));
+  const double fn = sqrt(block_sum(b, red));
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int64_t e = threadIdx.x; e < N; e += blockDim.x) V0[e] = r[e] * inv;
+  for (int i = threadIdx.x; i < gl; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
+  if (threadIdx.x == 0) {
+    out[0] = beta;
+    out[1] = fn;
+  }
+}
+
+// out[idx] = ||y - f|| / ||f||  (residual indicator of the current core)
+__global__ __launch_bounds__(1024) void rel_res_kernel(const double* __restrict__ y,
+                                                       const double* __restrict__ f, int64_t N,
+                                                       double* __restrict__ out) {
+  __shared__ double red[16];
+  double a = 0.0, b = 0.0;
+  for (int64_t e = threadIdx.x; e < N; e += blockDim.x) {
+    const double t = y[e] - f[e];
+    a = fma(t, t, a);
+    b = fma(f[e], f[e], b);
+  }
+  a = block_sum(a, red);
+  b = block_sum(b, red);
+  if (threadIdx.x == 0) *out = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+}
+
+// k_new = k * num / den ; outputs on device: kinfo[0] = k_new, kinfo[1] = k_old.
+__global__ void k_update_kernel(double* kval, const double* num, const double* den,
+                                double* kinfo) {
+  if (threadIdx.x == 0) {
+    const double k = *kval;
+    const double kn = k * (*num) / (*den);
+    kinfo[0] = kn;
+    kinfo[1] = k;
+    *kval = kn;
+  }
+}
+
+// den_next = num / sqrt(nrm2)
+__global__ void scale_ratio_kernel(const double* num, const double* nrm2, double* out) {
+  if (threadIdx.x == 0) *out = *num / sqrt(*nrm2);
+}
+
+}  // namespace
+
+void tt_core_matvec(hipStream_t s, const double* A, int R0, int m, int n, int R1,
+                    const double* X, int r0, int r1, double* Y) {
+  const int64_t total = (int64_t)R0 * r0 * m * R1 * r1;
+  if (total <= 0) return;
+  ++g_launches;
+  core_matvec_kernel<<<grid_for(total, 256), 256, 0, s>>>(A, R0, m, n, R1, X, r0, r1, Y);
+  TT_HIP(hipGetLastError());
+}
+
+void permute_op(hipStream_t s, const double* A, int RL, int m, int n, int RR, double* Ap) {
+  const int64_t total = (int64_t)RL * m * n * RR;
+  if (total <= 0) return;
+  ++g_launches;
+  permute_op_kernel<<<grid_for(total, 256), 256, 0, s>>>(A, RL, m, n, RR, Ap);
+  TT_HIP(hipGetLastError());
+}
+
+void local_matrix(hipStream_t s, const double* phiL, int ra, int RL, const double* P, int m,
+                  int n, int rc, double* M) {
+  const int64_t total = (int64_t)ra * m * rc * ra * n * rc;
+  if (total <= 0) return;
+  ++g_launches;
+  local_matrix_kernel<<<grid_for(total, 256), 256, 0, s>>>(phiL, ra, RL, P, m, n, rc, M);
+  TT_HIP(hipGetLastError());
+}
+
+void op_diag(hipStream_t s, const double* A, int RL, int n, int RR, double* Hd) {
+  ++g_launches;
+  op_diag_kernel<<<grid_for((int64_t)RL * n * RR, 256), 256, 0, s>>>(A, RL, n, RR, Hd);
+  TT_HIP(hipGetLastError());
+}
+
+void local_matrix_diag(hipStream_t s, const double* phiL, int ra, int RL, const double* P, int n,
+                       int rc, double* M) {
+  const int64_t total = (int64_t)n * ra * rc * ra * rc;
+  ++g_launches;
+  local_matrix_diag_kernel<<<grid_for(total, 256), 256, 0, s>>>(phiL, ra, RL, P, n, rc, M);
+  TT_HIP(hipGetLastError());
+}
+
+void swap_mode(hipStream_t s, const double* src, int ra, int n, int rc, double* dst,
+               bool to_blocks) {
+  ++g_launches;
+  swap_mode_kernel<<<grid_for((int64_t)ra * n * rc, 256), 256, 0, s>>>(src, ra, n, rc, dst,
+                                                                       to_blocks ? 1 : 0);
+  TT_HIP(hipGetLastError());
+}
+
+void scale_cols(hipStream_t s, double* X, int rows, int cols, int ld, const double* sv) {
+  if (rows <= 0 || cols <= 0) return;
+  ++g_launches;
+  scale_cols_kernel<<<grid_for((int64_t)rows * cols, 256), 256, 0, s>>>(X, rows, cols, ld, sv);
+  TT_HIP(hipGetLastError());
+}
+
+void arnoldi(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, double* cs,
+             double* sn, double* g, double* res) {
+  TT_REQUIRE(j + 2 <= 512, "Krylov dimension too large");
+  ++g_launches;
+  arnoldi_kernel<<<1, 1024, 0, s>>>(V, N, j, Hc, ldh, cs, sn, g, res);
+  TT_HIP(hipGetLastError());
+}
+
+void gmres_update(hipStream_t s, const double* V, int64_t N, int k, const double* Hc, int ldh,
+                  const double* g, double* x) {
+  if (k <= 0) return;
+  ++g_launches;
+  gmres_update_kernel<<<1, 1024, 0, s>>>(V, N, k, Hc, ldh, g, x);
+  TT_HIP(hipGetLastError());
+}
+
+void gmres_start(hipStream_t s, const double* f, double* r, int64_t N, double* V0, double* g,
+                 int gl, double* out) {
+  ++g_launches;
+  gmres_start_kernel<<<1, 1024, 0, s>>>(f, r, N, V0, g, gl, out);
+  TT_HIP(hipGetLastError());
+}
+
+void rel_res(hipStream_t s, const double* y, const double* f, int64_t N, double* out) {
+  ++g_launches;
+  rel_res_kernel<<<1, 1024, 0, s>>>(y, f, N, out);
+  TT_HIP(hipGetLastError());
+}
+
+void k_update(hipStream_t s, double* kval, const double* num, const double* den, double* kinfo) {
+  ++g_launches;
+  k_update_kernel<<<1, 64, 0, s>>>(kval, num, den, kinfo);
+  TT_HIP(hipGetLastError());
+}
+
+void scale_ratio(hipStream_t s, const double* num, const double* nrm2, double* out) {
+  ++g_launches;
+  scale_ratio_kernel<<<1, 64, 0, s>>>(num, nrm2, out);
+  TT_HIP(hipGetLastError());
+}
+
+}  // namespace ttnt

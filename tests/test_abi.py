@@ -1,0 +1,111 @@
+"""C-ABI contract checks that need no GPU: symbols and host-side validation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2309_03347_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ttnt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(tt[a-z_]*|ttnt_version)\s*\(", text)
+    return sorted(set(n for n in names if n not in ("tt_status",)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = native.lib()
+    declared = _declared()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(native.EXPORTED)
+    assert lib.ttnt_version() == 10000
+
+
+def _host_vec(n, r, rcap):
+    n = np.array(n, dtype=np.int32)
+    r = np.array(r, dtype=np.int32)
+    rcap = np.array(rcap, dtype=np.int32)
+    off = np.zeros(len(n), dtype=np.int64)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    v = native.TTVec(len(n), n.ctypes.data_as(native.I32P), r.ctypes.data_as(native.I32P),
+                     rcap.ctypes.data_as(native.I32P), fake, off.ctypes.data_as(native.I64P))
+    return v, (n, r, rcap, off)
+
+
+def _host_mat(m, n, R):
+    m = np.array(m, dtype=np.int32)
+    n = np.array(n, dtype=np.int32)
+    R = np.array(R, dtype=np.int32)
+    off = np.zeros(len(m), dtype=np.int64)
+    A = native.TTMat(len(m), m.ctypes.data_as(native.I32P), n.ctypes.data_as(native.I32P),
+                     R.ctypes.data_as(native.I32P), ctypes.c_void_p(0x1000),
+                     off.ctypes.data_as(native.I64P))
+    return A, (m, n, R, off)
+
+
+def test_matvec_rejects_mismatched_modes():
+    lib = native.lib()
+    A, ka = _host_mat([2, 2], [2, 3], [1, 2, 1])
+    x, kx = _host_vec([2, 2], [1, 2, 1], [1, 2, 1])
+    y, ky = _host_vec([2, 2], [1, 1, 1], [1, 4, 1])
+    st = lib.tt_matvec(ctypes.byref(A), ctypes.byref(x), ctypes.byref(y), None)
+    assert st == native.TT_E_ARG
+    assert b"modes" in lib.tt_last_error()
+
+
+def test_matvec_reports_capacity():
+    lib = native.lib()
+    A, ka = _host_mat([2, 2], [2, 2], [1, 3, 1])
+    x, kx = _host_vec([2, 2], [1, 2, 1], [1, 2, 1])
+    y, ky = _host_vec([2, 2], [1, 1, 1], [1, 5, 1])   # needs 6
+    assert lib.tt_matvec(ctypes.byref(A), ctypes.byref(x), ctypes.byref(y), None) == native.TT_E_CAPACITY
+    assert ky[1].tolist() == [1, 1, 1]    # nothing written
+
+
+def test_round_rejects_bad_arguments():
+    lib = native.lib()
+    x, kx = _host_vec([2, 2], [1, 3, 1], [1, 2, 1])    # rank above capacity
+    st = lib.tt_round(ctypes.byref(x), 1e-8, 4, None, ctypes.c_void_p(0x1000), 1 << 20, None)
+    assert st == native.TT_E_ARG
+    x, kx = _host_vec([2, 2], [1, 2, 1], [1, 2, 1])
+    st = lib.tt_round(ctypes.byref(x), -1.0, 4, None, ctypes.c_void_p(0x1000), 1 << 20, None)
+    assert st == native.TT_E_ARG
+    st = lib.tt_round(ctypes.byref(x), 1e-8, 0, None, ctypes.c_void_p(0x1000), 1 << 20, None)
+    assert st == native.TT_E_ARG
+    st = lib.tt_round(ctypes.byref(x), 1e-8, 4, None, ctypes.c_void_p(0x1000), 8, None)
+    assert st == native.TT_E_CAPACITY
+
+
+def test_local_solve_rejects_non_square():
+    lib = native.lib()
+    sysd = native.TTLocal(2, 1, 2, 3, 1, 2, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), ctypes.c_void_p(8))
+    opts = native.TTSolveOpts(0, 1e-10, 10, 10, 64)
+    info = native.TTSolveInfo()
+    st = lib.tt_local_solve(ctypes.byref(sysd), ctypes.c_void_p(8), ctypes.byref(opts),
+                            ctypes.byref(info), ctypes.c_void_p(8), 1 << 30, None)
+    assert st == native.TT_E_ARG
+
+
+def test_solver_rejects_bad_options():
+    lib = native.lib()
+    H, kh = _host_mat([2], [2], [1, 1])
+    SF, ks = _host_mat([2], [2], [1, 1])
+    cF, kc = _host_vec([2], [1, 1], [1, 1])
+    p0, kp = _host_vec([2], [1, 1], [1, 1])
+    prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, 1.0)
+    opts = native.TTSolverOpts(1e-8, 0, 4, 10, 0, 0, 0.0, 40, 100, 64)   # rmax = 0
+    h = ctypes.c_void_p()
+    assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
+    opts = native.TTSolverOpts(1e-8, 4, 4, 10, 7, 0, 0.0, 40, 100, 64)   # bad rhs_mode
+    assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
+    prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, -1.0)  # k0 <= 0
+    opts = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64)
+    assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
