@@ -1,0 +1,161 @@
+"""Benchmark: TT/QTT power-iteration steps per second on one MI355X.
+
+Workload (default): 32^3 nodes, 4 energy groups, S4 level-symmetric
+(24 directions), vacuum boundaries, two-region material with a seeded
+random inner box, TT rank cap 32, truncation tolerance 1e-8, FP64.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+
+Prints one JSON line.  `value` is power-iteration steps per second over K
+timed steps (inputs resident in HBM, after W untimed steps).  The roofline
+object reports the dominant kernel class timed with HIP events recorded on
+the solver's stream during a second pass of K steps; `cpu_baseline` is the
+plain FP64 checker (transport sweeps) timed on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline fraction
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+WORKLOADS = {
+    # name: (builder, description)
+    "inner_box_n32_G4_S4": (lambda W: W.config(1),
+                            "32^3 nodes, 4 groups, S4 (24 dirs), two-region, rank cap 32, tol 1e-8"),
+    "homogeneous_n8_S2": (lambda W: W.config(0),
+                          "8^3 nodes, 1 group, S2 (8 dirs), homogeneous, rank cap 8, tol 1e-10"),
+}
+
+
+def _parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="inner_box_n32_G4_S4", choices=sorted(WORKLOADS))
+    p.add_argument("--rmax", type=int, default=0, help="override the rank cap (0: workload's)")
+    p.add_argument("--rhs-mode", type=int, default=0, help="0 projected, 1 explicit")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-probe", action="store_true")
+    return p.parse_args()
+
+
+def _cpu_baseline(wl, seconds: float):
+    """The checker's exact power iteration, timed for about `seconds`."""
+    import numpy as np
+    from oracle import sweep
+    prob = sweep.Problem.from_workload(wl)
+    psi = sweep.dense_psi0(wl)
+    k = 1.0
+    nxt, k = prob.power_step(psi, k)           # warm (page-in, thread pool)
+    psi = nxt / np.linalg.norm(nxt)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        nxt, k = prob.power_step(psi, k)
+        psi = nxt / np.linalg.norm(nxt)
+        steps += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
+                sample=f"{steps} exact sweep power steps of the same workload "
+                       f"({prob.n_unknowns} unknowns) in {dt:.1f} s")
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the batch and "
+              "single-instance paths are single-device by design.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2309_03347_amd import workload as W
+    from paper_2309_03347_amd.solver import KeffSolver
+
+    builder, desc = WORKLOADS[args.workload]
+    wl = builder(W)
+    rmax = args.rmax or wl.rmax
+    s = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode)
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps / dt
+    hist = s.history
+
+    roofline = None
+    probe = None
+    if not args.no_probe:
+        s.native.set_probe(True)
+        for _ in range(args.steps):
+            s.step()
+        torch.cuda.synchronize()
+        probe = s.native.probe_stats()
+        s.native.set_probe(False)
+        # dominant kernel class by total device time
+        name, st = max(probe.items(), key=lambda kv: kv[1]["total_ms"])
+        avg_ms = st["total_ms"] / max(1, st["launches"])
+        if name.startswith("gemm"):
+            achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
+            roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                            frac=achieved / PEAK_FP64_TFLOPS, traffic=None)
+        else:
+            achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
+            roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                            frac=achieved / PEAK_HBM_GBS, traffic=None)
+        roofline.update(kernel=name, launches=st["launches"], avg_us=avg_ms * 1e3,
+                        flops_per_launch=st["flops"] / max(1, st["launches"]),
+                        bytes_per_launch=st["bytes"] / max(1, st["launches"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = _cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": "power-iteration steps/sec & time-to-k at 1e-5, mixed vs FP64; TT GFLOP/s % peak",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded)",
+        "config": {"workload": args.workload, "description": desc, "rank_cap": rmax,
+                   "tol": wl.tol, "rhs_mode": "projected" if args.rhs_mode == 0 else "explicit",
+                   "unknowns": int(wl.G * wl.L * wl.n ** 3)},
+        "k": hist[-1].k,
+        "dk_last": hist[-1].dk,
+        "max_rank": int(max(s.native.ranks())),
+        "sweeps_last": hist[-1].sweeps,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if probe is not None:
+        out["kernel_probe"] = {k: dict(launches=v["launches"], ms=round(v["total_ms"], 3))
+                               for k, v in probe.items() if v["launches"]}
+    print(json.dumps(out))
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

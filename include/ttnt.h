@@ -229,6 +229,26 @@ tt_status tt_solver_ranks(tt_solver* s, int32_t* ranks, int32_t* d);
 int64_t tt_solver_launches(tt_solver* s);
 tt_status tt_solver_destroy(tt_solver* s);
 
+/*
+ * Kernel probe (measurement aid, off by default).  When on, every launch of
+ * the timed kernel classes inside tt_power_step is bracketed by HIP events
+ * recorded on the step's stream, and the elapsed times are accumulated with
+ * the launch's algorithmic work: for a GEMM, 2 M N K flops and the bytes of
+ * reading A and B once and writing C once.  Classes: 0..3 the FP64 GEMM
+ * (no transpose, transposed A, transposed B, both), 4 the Krylov (Arnoldi)
+ * step, 5 the TT core matvec.  set_probe resets the totals.
+ */
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double flops;
+  double bytes;
+  int64_t dropped;       /* launches not timed because the event pool was full */
+} tt_probe_stats;
+
+tt_status tt_solver_set_probe(tt_solver* s, int32_t on);
+tt_status tt_solver_probe_stats(tt_solver* s, int32_t kernel_class, tt_probe_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

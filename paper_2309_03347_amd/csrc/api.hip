@@ -280,6 +280,27 @@ tt_status tt_solver_ranks(tt_solver* s, int32_t* ranks, int32_t* d) {
 
 int64_t tt_solver_launches(tt_solver* s) { return s ? s->impl.last_launches : -1; }
 
+tt_status tt_solver_set_probe(tt_solver* s, int32_t on) {
+  return guard([&] {
+    TT_REQUIRE(s != nullptr, "NULL solver");
+    s->impl.probe.active = on != 0;
+    s->impl.probe.reset();
+  });
+}
+
+tt_status tt_solver_probe_stats(tt_solver* s, int32_t kernel_class, tt_probe_stats* out) {
+  return guard([&] {
+    TT_REQUIRE(s && out, "NULL argument");
+    TT_REQUIRE(kernel_class >= 0 && kernel_class < kProbeClasses, "kernel_class out of range");
+    const Probe& p = s->impl.probe;
+    out->launches = p.n[kernel_class];
+    out->total_ms = p.ms[kernel_class];
+    out->flops = p.fl[kernel_class];
+    out->bytes = p.by[kernel_class];
+    out->dropped = (int64_t)p.dropped;
+  });
+}
+
 tt_status tt_solver_destroy(tt_solver* s) {
   delete s;
   return TT_OK;

@@ -2,6 +2,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "probe.h"
 
 namespace ttnt {
 
@@ -213,6 +214,12 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, co
   dim3 grid(cdiv(N, BN), cdiv(M, BM), batch * nsplit);
   TT_REQUIRE(grid.y <= 65535 && grid.z <= 65535, "gemm grid too large");
   ++g_launches;
+  hipEvent_t pe = nullptr;
+  if (g_probe) {
+    const double fl = 2.0 * M * N * (double)K * batch;
+    const double by = 8.0 * batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1));
+    pe = g_probe->begin(s, (ta ? 1 : 0) + (tb ? 2 : 0), fl, by);
+  }
   if (!ta && !tb)
     gemm_kernel<false, false><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
   else if (ta && !tb)
@@ -222,6 +229,7 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, co
   else
     gemm_kernel<true, true><<<grid, GT, 0, s>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, out, ldc, sC, nsplit, kchunk, batch);
   TT_HIP(hipGetLastError());
+  if (pe) g_probe->end(s);
   if (nsplit > 1) {
     ++g_launches;
     splitk_reduce_kernel<<<grid_for((int64_t)M * N * batch, 256), 256, 0, s>>>(

@@ -7,6 +7,7 @@
 #include "engine.h"
 #include "kernels.h"
 #include "ttk.h"
+#include "probe.h"
 
 namespace ttnt {
 
@@ -271,7 +272,7 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
     need += N * N + (int64_t)op.RL * op.m * op.n * op.rc * op.rc + 64;
   } else {
     const int m = o.restart;
-    need += (int64_t)(m + 1) * N + N + (int64_t)(m + 1) * (m + 1) + 3 * (m + 2) + 64;
+    need += (int64_t)(m + 1) * N + N + (int64_t)(m + 1) * (m + 1) + 4 * (m + 2) + 64;
   }
   need += N + 16;
   return (size_t)need + 1024;
@@ -314,13 +315,14 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     lu_solve(s, M, (int)N, (int)N, x);
   } else {
     res.method = 2;
-    const int m = std::max(2, std::min(o.restart, 500));
+    const int m = std::max(2, std::min(o.restart, 88));
     double* V = ws.d((int64_t)(m + 1) * N);
     double* r = ws.d(N);
     double* Hc = ws.d((int64_t)(m + 1) * (m + 1));
     double* cs = ws.d(m + 2);
     double* sn = ws.d(m + 2);
     double* g = ws.d(m + 2);
+    double* resv = ws.d(m + 2);
     double host[2];
     int total = 0;
     bool conv = false;
@@ -342,19 +344,26 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
         conv = host[0] <= target;
         break;
       }
+      // Arnoldi steps; the residual estimates are read back every kCheck
+      // steps and the solution uses the first step that met the target.
+      constexpr int kCheck = 4;
       int j = 0;
-      for (; j < m && total < o.max_iter; ++j) {
-        local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
-        arnoldi(s, V, N, j, Hc, m + 1, cs, sn, g, scal + 2);
-        ++total;
-        double est = 0.0;
-        TT_HIP(hipMemcpyAsync(&est, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-        TT_HIP(hipStreamSynchronize(s));
-        if (est <= target) {
-          ++j;
-          conv = true;
-          break;
+      while (j < m && total < o.max_iter && !conv) {
+        const int j0 = j;
+        for (int q = 0; q < kCheck && j < m && total < o.max_iter; ++q, ++j, ++total) {
+          local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
+          arnoldi(s, V, N, j, Hc, m + 1, cs, sn, g, resv + j);
         }
+        double est[kCheck];
+        TT_HIP(hipMemcpyAsync(est, resv + j0, (j - j0) * sizeof(double), hipMemcpyDeviceToHost, s));
+        TT_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < j - j0; ++q)
+          if (est[q] <= target) {
+            total -= (j - j0) - (q + 1);
+            j = j0 + q + 1;
+            conv = true;
+            break;
+          }
       }
       gmres_update(s, V, N, j, Hc, m + 1, g, x);
       if (conv || total >= o.max_iter) break;

@@ -1,6 +1,7 @@
 // Small dense factorizations used by TT rounding and the alternating solve.
 // Each runs in one workgroup of 1024 threads (16 wavefronts) on global memory
 // (the matrices are small and stay in cache).
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -9,15 +10,30 @@ namespace ttnt {
 namespace {
 
 constexpr int WG = 1024;
+// Dynamic LDS budget of the single-workgroup factorizations (doubles).
+constexpr int kLdsDoubles = 8000;
 
 // Householder QR: A (m x n) -> Q (m x k), R (k x n), k = min(m, n), diag(R) >= 0.
-__global__ __launch_bounds__(WG) void qr_kernel(double* __restrict__ A, int m, int n, int lda,
-                                                double* __restrict__ Q, int ldq,
+__global__ __launch_bounds__(WG) void qr_kernel(double* __restrict__ Ag, int m, int n, int ldag,
+                                                double* __restrict__ Qg, int ldqg,
                                                 double* __restrict__ R, int ldr,
-                                                double* __restrict__ tau) {
+                                                double* __restrict__ tau, int use_lds) {
   __shared__ double red[WG / 64];
+  extern __shared__ double sm[];
   const int k = min(m, n);
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
+  // working copies: in LDS when they fit, else the caller's buffers
+  double* A = Ag;
+  double* Q = Qg;
+  int lda = ldag, ldq = ldqg;
+  if (use_lds) {
+    A = sm;
+    Q = sm + m * n;
+    lda = n;
+    ldq = k;
+    for (int e = tid; e < m * n; e += nt) A[e] = Ag[(int64_t)(e / n) * ldag + e % n];
+    __syncthreads();
+  }
   for (int j = 0; j < k; ++j) {
     double v = 0.0;
     for (int i = j + 1 + tid; i < m; i += nt) {
@@ -87,6 +103,10 @@ __global__ __launch_bounds__(WG) void qr_kernel(double* __restrict__ A, int m, i
     const int i = (int)(e / k), c = (int)(e % k);
     Q[(int64_t)i * ldq + c] *= tau[c];
   }
+  if (use_lds) {
+    __syncthreads();
+    for (int e = tid; e < m * k; e += nt) Qg[(int64_t)(e / k) * ldqg + e % k] = Q[e];
+  }
 }
 
 __device__ __forceinline__ int rr_player(int pos, int round, int np) {
@@ -98,9 +118,10 @@ __global__ __launch_bounds__(WG) void svd_kernel(const double* __restrict__ G, i
                                                  int ldg, double* __restrict__ U, int ldu,
                                                  double* __restrict__ S,
                                                  double* __restrict__ V, int ldv,
-                                                 double* __restrict__ work) {
+                                                 double* __restrict__ work, int use_lds) {
   __shared__ int s_rot;
-  double* Gt = work;
+  extern __shared__ double sm[];
+  double* Gt = use_lds ? sm : work;
   double* Vt = Gt + (int64_t)n * m;
   double* sig = Vt + (int64_t)n * n;
   double* rk = sig + n;
@@ -228,10 +249,22 @@ __global__ void trunc_rank_kernel(const double* __restrict__ S, int n, double to
 }
 
 // Dense LU with partial pivoting and solve, in place (A N x N, b length N).
-__global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ A, int N, int lda,
-                                                      double* __restrict__ b) {
-  A += (int64_t)blockIdx.x * N * lda;
-  b += (int64_t)blockIdx.x * N;
+__global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, int N, int ldag,
+                                                      double* __restrict__ bg, int use_lds) {
+  extern __shared__ double sm[];
+  Ag += (int64_t)blockIdx.x * N * ldag;
+  bg += (int64_t)blockIdx.x * N;
+  double* A = Ag;
+  double* b = bg;
+  int lda = ldag;
+  if (use_lds) {
+    A = sm;
+    b = sm + N * N;
+    lda = N;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = Ag[(int64_t)(e / N) * ldag + e % N];
+    for (int e = threadIdx.x; e < N; e += blockDim.x) b[e] = bg[e];
+    __syncthreads();
+  }
   __shared__ double sval[WG / 64];
   __shared__ int sidx[WG / 64];
   __shared__ int s_piv;
@@ -294,6 +327,8 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ A, in
     for (int r = tid; r < i; r += nt) b[r] -= A[(int64_t)r * lda + i] * xi;
     __syncthreads();
   }
+  if (use_lds)
+    for (int e = tid; e < N; e += nt) bg[e] = b[e];
 }
 
 }  // namespace
@@ -302,7 +337,9 @@ void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, dou
         double* tau) {
   if (m <= 0 || n <= 0) return;
   ++g_launches;
-  qr_kernel<<<1, WG, 0, s>>>(A, m, n, lda, Q, ldq, R, ldr, tau);
+  const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
+  qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
+      A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 
@@ -313,7 +350,9 @@ void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, do
   if (m <= 0 || n <= 0) return;
   TT_REQUIRE(m >= n, "svd expects m >= n");
   ++g_launches;
-  svd_kernel<<<1, WG, 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work);
+  const size_t need = svd_work_doubles(m, n);
+  const bool lds = need <= (size_t)kLdsDoubles;
+  svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 
@@ -327,7 +366,9 @@ void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,
 void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   if (N <= 0 || batch <= 0) return;
   ++g_launches;
-  lu_solve_kernel<<<batch, WG, 0, s>>>(A, N, lda, b);
+  const bool lds = (int64_t)N * N + N <= kLdsDoubles;
+  lu_solve_kernel<<<batch, WG, lds ? (size_t)((int64_t)N * N + N) * 8 : 0, s>>>(A, N, lda, b,
+                                                                                 lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "engine.h"
+#include "probe.h"
 
 namespace ttnt {
 
@@ -25,6 +26,7 @@ struct Solver {
   double stall = 0.5;          // stop sweeping when the residual falls by less than this
   std::vector<char> Hdiag;
   int64_t last_launches = 0;
+  Probe probe;
 
   void* mem = nullptr;
   size_t mem_bytes = 0;

@@ -7,6 +7,7 @@
 #include "engine.h"
 #include "kernels.h"
 #include "solver.h"
+#include "probe.h"
 #include "ttk.h"
 
 namespace ttnt {
@@ -463,6 +464,11 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
     SplitScope(double* p, size_t c) { g_splitk_buf = p; g_splitk_cap = c; }
     ~SplitScope() { g_splitk_buf = nullptr; g_splitk_cap = 0; }
   } split_scope(splitk, kSplitK);
+  struct ProbeScope {
+    explicit ProbeScope(Probe* p) { g_probe = p; }
+    ~ProbeScope() { g_probe = nullptr; }
+  } probe_scope(probe.active ? &probe : nullptr);
+  if (probe.active && probe.overhead_ms == 0.0) probe.calibrate(s);
   StepStats st;
   // A(k) core 0 = SF_0 + F_0 / k
   copy(s, F0, A0, SF.size(0));
@@ -532,6 +538,7 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
   TT_HIP(hipMemcpyAsync(kinfo, scal + KINFO, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   TT_HIP(hipStreamSynchronize(s));
   k_host = kinfo[0];
+  if (probe.active) probe.close();
   if (info) {
     info->k = kinfo[0];
     info->k_prev = kinfo[1];

@@ -2,6 +2,7 @@
 // matrix, Krylov (Arnoldi) step, small vector helpers.
 #include "kernels.h"
 #include "ttk.h"
+#include "probe.h"
 
 namespace ttnt {
 namespace {
@@ -152,19 +153,39 @@ __global__ __launch_bounds__(1024) void arnoldi_kernel(double* __restrict__ V, i
   for (int pass = 0; pass < 2; ++pass) {
     for (int i = wid; i <= j; i += nw) {
       const double* vi = V + (int64_t)i * N;
-      double acc = 0.0;
-      for (int64_t e = lane; e < N; e += 64) acc = fma(vi[e], w[e], acc);
-      acc = wave_sum(acc);
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int64_t e = lane;
+      for (; e + 192 < N; e += 256) {
+        a0 = fma(vi[e], w[e], a0);
+        a1 = fma(vi[e + 64], w[e + 64], a1);
+        a2 = fma(vi[e + 128], w[e + 128], a2);
+        a3 = fma(vi[e + 192], w[e + 192], a3);
+      }
+      for (; e < N; e += 64) a0 = fma(vi[e], w[e], a0);
+      const double acc = wave_sum((a0 + a1) + (a2 + a3));
       if (lane == 0) h[512 + i] = acc;
     }
     __syncthreads();
     for (int64_t e = tid; e < N; e += nt) {
-      double acc = w[e];
-      for (int i = 0; i <= j; ++i) acc -= h[512 + i] * V[(int64_t)i * N + e];
-      w[e] = acc;
+      double a0 = w[e], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int i = 0;
+      for (; i + 3 <= j; i += 4) {
+        a0 -= h[512 + i] * V[(int64_t)i * N + e];
+        a1 -= h[513 + i] * V[(int64_t)(i + 1) * N + e];
+        a2 -= h[514 + i] * V[(int64_t)(i + 2) * N + e];
+        a3 -= h[515 + i] * V[(int64_t)(i + 3) * N + e];
+      }
+      for (; i <= j; ++i) a0 -= h[512 + i] * V[(int64_t)i * N + e];
+      w[e] = (a0 + a1) + (a2 + a3);
     }
     for (int i = tid; i <= j; i += nt) h[i] += h[512 + i];
     __syncthreads();
+  }
+  // stage the previous rotations in LDS (the serial update below reads them)
+  __shared__ double rc[512], rs[512];
+  for (int i = tid; i < j; i += nt) {
+    rc[i] = cs[i];
+    rs[i] = sn[i];
   }
   double v = 0.0;
   for (int64_t e = tid; e < N; e += nt) v = fma(w[e], w[e], v);
@@ -174,8 +195,8 @@ __global__ __launch_bounds__(1024) void arnoldi_kernel(double* __restrict__ V, i
   if (tid == 0) {
     h[j + 1] = nrm;
     for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-      h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+      const double t = rc[i] * h[i] + rs[i] * h[i + 1];
+      h[i + 1] = -rs[i] * h[i] + rc[i] * h[i + 1];
       h[i] = t;
     }
     const double a = h[j], b = h[j + 1];
@@ -198,16 +219,26 @@ __global__ __launch_bounds__(1024) void gmres_update_kernel(const double* __rest
                                                             const double* __restrict__ Hc,
                                                             int ldh, const double* __restrict__ g,
                                                             double* __restrict__ x) {
-  __shared__ double y[1024];
-  if (threadIdx.x == 0) {
-    for (int i = k - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int c = i + 1; c < k; ++c) acc -= Hc[(int64_t)c * ldh + i] * y[c];
-      const double d = Hc[(int64_t)i * ldh + i];
-      y[i] = d != 0.0 ? acc / d : 0.0;
-    }
+  __shared__ double y[128];
+  __shared__ double gs[128];
+  extern __shared__ double Hs[];      // k x k upper triangle, column-major like Hc
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int c = e / k, i = e % k;
+    Hs[e] = i <= c ? Hc[(int64_t)c * ldh + i] : 0.0;
   }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
   __syncthreads();
+  // column-oriented back substitution: one division, then a parallel update
+  for (int i = k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const double d = Hs[i * k + i];
+      y[i] = d != 0.0 ? gs[i] / d : 0.0;
+    }
+    __syncthreads();
+    const double yi = y[i];
+    for (int r = threadIdx.x; r < i; r += blockDim.x) gs[r] -= Hs[i * k + r] * yi;
+    __syncthreads();
+  }
   for (int64_t e = threadIdx.x; e < N; e += blockDim.x) {
     double acc = x[e];
     for (int i = 0; i < k; ++i) acc = fma(y[i], V[(int64_t)i * N + e], acc);
@@ -280,8 +311,15 @@ void tt_core_matvec(hipStream_t s, const double* A, int R0, int m, int n, int R1
   const int64_t total = (int64_t)R0 * r0 * m * R1 * r1;
   if (total <= 0) return;
   ++g_launches;
+  hipEvent_t pe = nullptr;
+  if (g_probe) {
+    const double fl = 2.0 * (double)total * n;
+    const double by = 8.0 * ((double)total + (double)R0 * m * n * R1 + (double)r0 * n * r1);
+    pe = g_probe->begin(s, kProbeMatvec, fl, by);
+  }
   core_matvec_kernel<<<grid_for(total, 256), 256, 0, s>>>(A, R0, m, n, R1, X, r0, r1, Y);
   TT_HIP(hipGetLastError());
+  if (pe) g_probe->end(s);
 }
 
 void permute_op(hipStream_t s, const double* A, int RL, int m, int n, int RR, double* Ap) {
@@ -334,15 +372,24 @@ void arnoldi(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, do
              double* sn, double* g, double* res) {
   TT_REQUIRE(j + 2 <= 512, "Krylov dimension too large");
   ++g_launches;
+  hipEvent_t pe = nullptr;
+  if (g_probe) {
+    // two classical Gram-Schmidt passes: dots and updates over j+1 vectors
+    const double fl = 8.0 * (double)N * (j + 1) + 3.0 * N;
+    const double by = 8.0 * (double)N * (2.0 * (j + 1) + 4.0);
+    pe = g_probe->begin(s, kProbeArnoldi, fl, by);
+  }
   arnoldi_kernel<<<1, 1024, 0, s>>>(V, N, j, Hc, ldh, cs, sn, g, res);
   TT_HIP(hipGetLastError());
+  if (pe) g_probe->end(s);
 }
 
 void gmres_update(hipStream_t s, const double* V, int64_t N, int k, const double* Hc, int ldh,
                   const double* g, double* x) {
   if (k <= 0) return;
+  TT_REQUIRE(k <= 88, "Krylov dimension above the LDS budget of the update");
   ++g_launches;
-  gmres_update_kernel<<<1, 1024, 0, s>>>(V, N, k, Hc, ldh, g, x);
+  gmres_update_kernel<<<1, 1024, (size_t)k * k * 8, s>>>(V, N, k, Hc, ldh, g, x);
   TT_HIP(hipGetLastError());
 }
 

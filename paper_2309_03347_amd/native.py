@@ -23,7 +23,8 @@ _NAMES = {0: "TT_OK", -1: "TT_E_ARG", -2: "TT_E_CAPACITY", -3: "TT_E_NOCONV",
 EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", "tt_round",
             "tt_dot_workspace", "tt_dot", "tt_local_solve_workspace", "tt_local_solve",
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
-            "tt_solver_launches", "tt_solver_destroy"]
+            "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
+            "tt_solver_probe_stats"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -81,6 +82,16 @@ class TTSolverOpts(ctypes.Structure):
                 ("direct_max", ctypes.c_int32)]
 
 
+class TTProbeStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("dropped", ctypes.c_int64)]
+
+
+PROBE_CLASSES = {0: "gemm_nn", 1: "gemm_tn", 2: "gemm_nt", 3: "gemm_tt", 4: "arnoldi",
+                 5: "core_matvec"}
+
+
 class TTStepInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_double), ("k_prev", ctypes.c_double), ("dk", ctypes.c_double),
                 ("max_local_res", ctypes.c_double), ("trunc_err", ctypes.c_double),
@@ -124,6 +135,8 @@ def lib():
         L.tt_solver_launches.argtypes = [v]
         L.tt_solver_launches.restype = ctypes.c_int64
         L.tt_solver_destroy.argtypes = [v]
+        L.tt_solver_set_probe.argtypes = [v, ctypes.c_int32]
+        L.tt_solver_probe_stats.argtypes = [v, ctypes.c_int32, ctypes.POINTER(TTProbeStats)]
         for name in EXPORTED:
             if name not in ("ttnt_version", "tt_last_error", "tt_round_workspace",
                             "tt_dot_workspace", "tt_local_solve_workspace",
@@ -329,6 +342,18 @@ class Solver:
 
     def launches(self) -> int:
         return int(lib().tt_solver_launches(self.h))
+
+    def set_probe(self, on: bool):
+        _check(lib().tt_solver_set_probe(self.h, 1 if on else 0))
+
+    def probe_stats(self) -> dict:
+        out = {}
+        for c, name in PROBE_CLASSES.items():
+            st = TTProbeStats()
+            _check(lib().tt_solver_probe_stats(self.h, c, ctypes.byref(st)))
+            out[name] = dict(launches=st.launches, total_ms=st.total_ms, flops=st.flops,
+                             bytes=st.bytes, dropped=st.dropped)
+        return out
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
