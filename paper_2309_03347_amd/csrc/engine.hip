@@ -272,7 +272,8 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
     need += N * N + (int64_t)op.RL * op.m * op.n * op.rc * op.rc + 64;
   } else {
     const int m = o.restart;
-    need += (int64_t)(m + 1) * N + N + (int64_t)(m + 1) * (m + 1) + 4 * (m + 2) + 64;
+    need += (int64_t)(m + 1) * N + N + (int64_t)(m + 1) * (m + 1) + 4 * (m + 2) + 64 +
+            (int64_t)arnoldi_mwg_doubles(N, m);
   }
   need += N + 16;
   return (size_t)need + 1024;
@@ -323,6 +324,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     double* sn = ws.d(m + 2);
     double* g = ws.d(m + 2);
     double* resv = ws.d(m + 2);
+    double* awork = ws.d(arnoldi_mwg_doubles(N, m));
     double host[2];
     int total = 0;
     bool conv = false;
@@ -352,7 +354,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
         const int j0 = j;
         for (int q = 0; q < kCheck && j < m && total < o.max_iter; ++q, ++j, ++total) {
           local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
-          arnoldi(s, V, N, j, Hc, m + 1, cs, sn, g, resv + j);
+          arnoldi_mwg(s, V, N, j, Hc, m + 1, cs, sn, g, resv, awork);
         }
         double est[kCheck];
         TT_HIP(hipMemcpyAsync(est, resv + j0, (j - j0) * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -384,7 +384,11 @@ void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   Bump lw;
   lw.base = (char*)lsw;
   lw.cap = ls_cap;
-  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lso, lw, false);
+  // When the rank cap binds, the truncation error exceeds tol, so local
+  // solves only need to reduce their residual by a fixed factor.
+  LocalSolveOpts lo = lso;
+  if (cap_bound) lo.eta = cap_eta;
+  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lo, lw, false);
   st.local_iters += lr.iterations;
   if (k == d - 1) {
     copy(s, xloc, X.core(k), N);
@@ -518,6 +522,7 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
     ++sweeps;
     if (!(max_res == max_res)) throw NumericError{};
     if (max_res < tol) break;
+    cap_bound = st.cap_hit;
     // stagnation: the rank cap bound and the residual no longer falls
     if (st.cap_hit && sweeps >= 2 && max_res > stall * prev_res) break;
     prev_res = max_res;

@@ -21,6 +21,10 @@ void swap_mode(hipStream_t s, const double* src, int ra, int n, int rc, double* 
                bool to_blocks);
 void arnoldi(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, double* cs,
              double* sn, double* g, double* res);
+// Multi-workgroup Arnoldi step (CGS2 in four launches); res[j] = |g[j+1]|.
+size_t arnoldi_mwg_doubles(int64_t N, int m);
+void arnoldi_mwg(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, double* cs,
+                 double* sn, double* g, double* res, double* work);
 void gmres_update(hipStream_t s, const double* V, int64_t N, int k, const double* Hc, int ldh,
                   const double* g, double* x);
 void gmres_start(hipStream_t s, const double* f, double* r, int64_t N, double* V0, double* g,

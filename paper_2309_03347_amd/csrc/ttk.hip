@@ -4,6 +4,8 @@
 #include "ttk.h"
 #include "probe.h"
 
+#include <algorithm>
+
 namespace ttnt {
 namespace {
 
@@ -213,6 +215,122 @@ __global__ __launch_bounds__(1024) void arnoldi_kernel(double* __restrict__ V, i
   }
 }
 
+// ---- multi-workgroup Arnoldi step (CGS2), four launches ----
+// Workgroup b owns elements [b*chunk, min(N, (b+1)*chunk)); chunk is a
+// multiple of 64 so every lane of a wavefront has at most chunk/64 elements.
+// Partials: P1[b][i], P2[b][i] (dots of the two passes), P3[b] (norm^2),
+// hacc[i] (the accumulated Hessenberg column).
+
+__device__ __forceinline__ void chunk_dots(const double* __restrict__ V, const double* __restrict__ w,
+                                           int64_t N, int j, int64_t e0, int64_t e1,
+                                           double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wid; i <= j; i += nw) {
+    const double* vi = V + (int64_t)i * N;
+    double acc = 0.0;
+    for (int64_t e = e0 + lane; e < e1; e += 64) acc = fma(vi[e], w[e], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) out[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void arn_dots_kernel(const double* __restrict__ V, int64_t N,
+                                                       int j, int64_t chunk,
+                                                       double* __restrict__ P1) {
+  const int b = blockIdx.x;
+  const int64_t e0 = b * chunk, e1 = min(N, e0 + chunk);
+  chunk_dots(V, V + (int64_t)(j + 1) * N, N, j, e0, e1, P1 + (int64_t)b * (j + 1));
+}
+
+// h = sum_b Pin[b][:];  w -= V^T h on this chunk;  then either the next dots
+// (Pout != null) or the partial norm^2 (P3).  Workgroup 0 accumulates h into hacc.
+__global__ __launch_bounds__(256) void arn_update_kernel(double* __restrict__ V, int64_t N, int j,
+                                                         int64_t chunk, int G,
+                                                         const double* __restrict__ Pin,
+                                                         double* __restrict__ Pout,
+                                                         double* __restrict__ P3,
+                                                         double* __restrict__ hacc, int first) {
+  __shared__ double h[128];
+  __shared__ double red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  for (int i = tid; i <= j; i += 256) {
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += Pin[(int64_t)q * (j + 1) + i];
+    h[i] = s;
+    if (b == 0) hacc[i] = first ? s : hacc[i] + s;
+  }
+  __syncthreads();
+  double* w = V + (int64_t)(j + 1) * N;
+  const int64_t e0 = b * chunk, e1 = min(N, e0 + chunk);
+  double nn = 0.0;
+  for (int64_t e = e0 + tid; e < e1; e += 256) {
+    double a0 = w[e], a1 = 0.0;
+    int i = 0;
+    for (; i + 1 <= j; i += 2) {
+      a0 -= h[i] * V[(int64_t)i * N + e];
+      a1 -= h[i + 1] * V[(int64_t)(i + 1) * N + e];
+    }
+    if (i <= j) a0 -= h[i] * V[(int64_t)i * N + e];
+    const double r = a0 + a1;
+    w[e] = r;
+    nn = fma(r, r, nn);
+  }
+  __syncthreads();
+  if (Pout) {
+    chunk_dots(V, w, N, j, e0, e1, Pout + (int64_t)b * (j + 1));
+  } else {
+    nn = wave_sum(nn);
+    if ((tid & 63) == 0) red[tid >> 6] = nn;
+    __syncthreads();
+    if (tid == 0) P3[b] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void arn_finish_kernel(double* __restrict__ V, int64_t N, int j,
+                                                         int64_t chunk, int G,
+                                                         const double* __restrict__ P3,
+                                                         const double* __restrict__ hacc,
+                                                         double* __restrict__ Hc, int ldh,
+                                                         double* __restrict__ cs,
+                                                         double* __restrict__ sn,
+                                                         double* __restrict__ g,
+                                                         double* __restrict__ res) {
+  __shared__ double snrm;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += P3[q];
+    snrm = sqrt(s);
+  }
+  __syncthreads();
+  const double nrm = snrm;
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  double* w = V + (int64_t)(j + 1) * N;
+  const int64_t e0 = b * chunk, e1 = min(N, e0 + chunk);
+  for (int64_t e = e0 + tid; e < e1; e += 256) w[e] *= inv;
+  if (b == 0 && tid == 0) {
+    double h[130];
+    for (int i = 0; i <= j; ++i) h[i] = hacc[i];
+    h[j + 1] = nrm;
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+      h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+      h[i] = t;
+    }
+    const double a = h[j], bb = h[j + 1];
+    const double rr = sqrt(a * a + bb * bb);
+    const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? bb / rr : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    h[j] = rr;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    double* hcol = Hc + (int64_t)j * ldh;
+    for (int i = 0; i <= j; ++i) hcol[i] = h[i];
+    res[j] = fabs(g[j + 1]);
+  }
+}
+
 // Solve the k x k upper-triangular least-squares system and update x += V^T y.
 __global__ __launch_bounds__(1024) void gmres_update_kernel(const double* __restrict__ V,
                                                             int64_t N, int k,
@@ -380,6 +498,42 @@ void arnoldi(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, do
     pe = g_probe->begin(s, kProbeArnoldi, fl, by);
   }
   arnoldi_kernel<<<1, 1024, 0, s>>>(V, N, j, Hc, ldh, cs, sn, g, res);
+  TT_HIP(hipGetLastError());
+  if (pe) g_probe->end(s);
+}
+
+namespace {
+int64_t arn_chunk(int64_t N) {
+  const int64_t per = (N + 127) / 128;                 // at most 128 workgroups
+  return std::max<int64_t>(64, (per + 63) / 64 * 64);
+}
+}  // namespace
+
+size_t arnoldi_mwg_doubles(int64_t N, int m) {
+  const int64_t G = (N + arn_chunk(N) - 1) / arn_chunk(N);
+  return (size_t)(2 * G * (m + 1) + G + m + 8);
+}
+
+void arnoldi_mwg(hipStream_t s, double* V, int64_t N, int j, double* Hc, int ldh, double* cs,
+                 double* sn, double* g, double* res, double* work) {
+  TT_REQUIRE(j + 2 <= 128, "Krylov dimension too large for the multi-workgroup step");
+  const int64_t chunk = arn_chunk(N);
+  const int G = (int)((N + chunk - 1) / chunk);
+  double* P1 = work;
+  double* P2 = P1 + (int64_t)G * (j + 1);
+  double* P3 = P2 + (int64_t)G * (j + 1);
+  double* hacc = P3 + G;
+  hipEvent_t pe = nullptr;
+  if (g_probe) {
+    const double fl = 8.0 * (double)N * (j + 1) + 3.0 * N;
+    const double by = 8.0 * (double)N * (2.0 * (j + 1) + 4.0);
+    pe = g_probe->begin(s, kProbeArnoldi, fl, by);
+  }
+  g_launches += 4;
+  arn_dots_kernel<<<G, 256, 0, s>>>(V, N, j, chunk, P1);
+  arn_update_kernel<<<G, 256, 0, s>>>(V, N, j, chunk, G, P1, P2, nullptr, hacc, 1);
+  arn_update_kernel<<<G, 256, 0, s>>>(V, N, j, chunk, G, P2, nullptr, P3, hacc, 0);
+  arn_finish_kernel<<<G, 256, 0, s>>>(V, N, j, chunk, G, P3, hacc, Hc, ldh, cs, sn, g, res);
   TT_HIP(hipGetLastError());
   if (pe) g_probe->end(s);
 }
