@@ -127,7 +127,9 @@ tt_status tt_dot(const tt_vec* a, const tt_vec* b, double* result, void* ws, siz
  * f and x [ra][n][rc] (all device, row-major).  x holds the initial guess
  * on input and the solution on output.  method: 0 automatic (dense LU when
  * ra*n*rc <= direct_max, else restarted GMRES), 1 dense LU with partial
- * pivoting, 2 GMRES.  info (host) receives iterations and the final relative
+ * pivoting, 2 GMRES (one persistent cooperative kernel per solve, restart
+ * length capped at 88), 4 GMRES with one launch per stage of each Arnoldi
+ * step (same arithmetic, for comparison).  info (host) receives iterations and the final relative
  * residual ||A x - f|| / ||f||.  Returns TT_E_NOCONV if GMRES stops at
  * max_iter above tol (x still written).  Synchronizes `stream`.
  */
@@ -140,7 +142,7 @@ typedef struct {
 } tt_local;
 
 typedef struct {
-  int32_t method;       /* 0 auto, 1 LU, 2 GMRES */
+  int32_t method;       /* 0 auto, 1 LU, 2 GMRES (persistent), 4 GMRES (per-stage launches) */
   double tol;           /* relative residual target for GMRES */
   int32_t max_iter;     /* total GMRES iterations */
   int32_t restart;      /* Krylov dimension per cycle */
@@ -236,7 +238,9 @@ tt_status tt_solver_destroy(tt_solver* s);
  * the launch's algorithmic work: for a GEMM, 2 M N K flops and the bytes of
  * reading A and B once and writing C once.  Classes: 0..3 the FP64 GEMM
  * (no transpose, transposed A, transposed B, both), 4 the Krylov (Arnoldi)
- * step, 5 the TT core matvec.  set_probe resets the totals.
+ * step of the per-stage GMRES, 5 the TT core matvec, 6 a whole persistent
+ * GMRES local solve (work: its operator applications and Gram-Schmidt
+ * passes, counted after it ran).  set_probe resets the totals.
  */
 typedef struct {
   int64_t launches;

@@ -1,6 +1,7 @@
 // Dense FP64 building blocks: batched GEMM, copies, reductions.
 #include <algorithm>
 
+#include "gemm_tile.h"
 #include "kernels.h"
 #include "probe.h"
 
@@ -12,13 +13,8 @@ thread_local size_t g_splitk_cap = 0;
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, GT = 256;
+constexpr int BM = kTileM, BN = kTileN, BK = kTileK, GT = 256;
 
-// 64x64 output tile per workgroup of 256 threads; each thread owns a 4x4
-// block (rows tr*4+i, columns tc+16*j so that C stores are coalesced).
-// With nsplit > 1 the workgroup sums only its slice of K and stores the raw
-// partial tile to C + (split * batch + b) * M * N (dense, ld N); a second
-// kernel reduces the slices in a fixed order (deterministic).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, double alpha,
                                                   const double* __restrict__ A, int lda,
@@ -26,76 +22,21 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, double al
                                                   int ldb, int64_t sB, double beta,
                                                   double* __restrict__ C, int ldc, int64_t sC,
                                                   int nsplit, int kchunk, int batch) {
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  __shared__ double As[kTileK][kTileM + 1];
+  __shared__ double Bs[kTileK][kTileN + 1];
   const int64_t bz = blockIdx.z % batch;
   const int split = blockIdx.z / batch;
-  A += bz * sA;
-  B += bz * sB;
   const int kb = split * kchunk;
   const int ke = min(K, kb + kchunk);
+  double* Cb;
   if (nsplit > 1) {
-    C += ((int64_t)split * batch + bz) * M * N;
+    Cb = C + ((int64_t)split * batch + bz) * M * N;
     ldc = N;
   } else {
-    C += bz * sC;
+    Cb = C + bz * sC;
   }
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-#pragma unroll
-    for (int t = 0; t < (BM * BK) / GT; ++t) {
-      const int e = tid + t * GT;
-      int mm, kk;
-      if (!TA) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < ke) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[kk][mm] = v;
-    }
-#pragma unroll
-    for (int t = 0; t < (BK * BN) / GT; ++t) {
-      const int e = tid + t * GT;
-      int kk, nn;
-      if (!TB) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
-      const int gk = k0 + kk, gn = n0 + nn;
-      double v = 0.0;
-      if (gk < ke && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + tr * 4 + i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tc + 16 * j;
-      if (gn >= N) continue;
-      double* c = C + (int64_t)gm * ldc + gn;
-      if (nsplit > 1) *c = acc[i][j];
-      else *c = beta == 0.0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * *c;
-    }
-  }
+  gemm_tile<TA, TB>(blockIdx.y, blockIdx.x, M, N, kb, ke, alpha, A + bz * sA, lda, B + bz * sB,
+                    ldb, beta, Cb, ldc, nsplit > 1, As, Bs);
 }
 
 // C[b][m][n] = alpha * sum_s P[s][b][m][n] + beta * C[b][m][n]  (fixed order in s)

@@ -41,7 +41,7 @@ struct NoConvError {};
     if (!(cond)) throw ::ttnt::ArgError{std::string(text)};       \
   } while (0)
 
-inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // Device reductions (64-lane wavefronts).

@@ -78,7 +78,7 @@ void local_apply(hipStream_t s, const LocalOp& op, const double* v, double* y, d
                  double beta, double* T1, double* T2);
 
 struct LocalSolveOpts {
-  int method = 0;          // 0 auto, 1 dense LU, 2 GMRES
+  int method = 0;          // 0 auto, 1 dense LU, 2 GMRES (persistent), 3 block LU, 4 GMRES (per-stage launches)
   double tol = 1e-10;      // relative residual target
   double eta = 0.0;        // GMRES also stops at ||r|| <= eta * ||r_0|| (0: off)
   int max_iter = 400;

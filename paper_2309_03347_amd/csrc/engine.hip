@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "engine.h"
+#include "krylov.h"
 #include "kernels.h"
 #include "ttk.h"
 #include "probe.h"
@@ -271,9 +272,12 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
   } else if (method == 1) {
     need += N * N + (int64_t)op.RL * op.m * op.n * op.rc * op.rc + 64;
   } else {
-    const int m = o.restart;
+    const int m = std::max(2, std::min(o.restart, 88));
     need += (int64_t)(m + 1) * N + N + (int64_t)(m + 1) * (m + 1) + 4 * (m + 2) + 64 +
             (int64_t)arnoldi_mwg_doubles(N, m);
+    const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
+    if (method == 2 && krylov_enabled())
+      need = std::max<int64_t>(need, t1 + t2 + 64 + 64 + krylov_ws_doubles(sh, m, krylov_grid()));
   }
   need += N + 16;
   return (size_t)need + 1024;
@@ -314,8 +318,41 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     local_matrix(s, op.phiL, op.ra, op.RL, P, op.m, op.n, op.rc, M);
     copy(s, f, x, N);
     lu_solve(s, M, (int)N, (int)N, x);
-  } else {
+  } else if (method == 2 && krylov_enabled() &&
+             krylov_fits(KrylovShape{op.ra, op.RL, op.n, op.RR, op.rc},
+                         std::max(2, std::min(o.restart, 88)))) {
     res.method = 2;
+    const int m = std::max(2, std::min(o.restart, 88));
+    const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
+    const int grid = krylov_grid();
+    const size_t kw = krylov_ws_doubles(sh, m, grid);
+    double* kws = ws.d(kw);
+    const bool probed = krylov_solve(s, sh, op.phiL, op.Ap, op.phiR, f, x, m, o.max_iter, o.tol,
+                                     o.eta, kws, kw, scal, grid);
+    double info[3];
+    TT_HIP(hipMemcpyAsync(info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TT_HIP(hipStreamSynchronize(s));
+    res.iterations = (int)info[0];
+    res.converged = info[1] != 0.0;
+    if (probed) {
+      // algorithmic work: one operator application per Arnoldi step and per
+      // restart residual, and the two Gram-Schmidt passes over j + 1 vectors
+      const int m = krylov_restart(sh, std::max(2, std::min(o.restart, 88)));
+      const int64_t T = res.iterations;
+      const int64_t full = T / m, rem = T % m;
+      const double sumj = (double)full * m * (m + 1) / 2 + (double)rem * (rem + 1) / 2;
+      const int64_t applies = T + std::max<int64_t>(1, (T + m - 1) / m);
+      const double fa = 2.0 * ((double)op.ra * op.RL * op.n * op.rd * op.rb +
+                               (double)op.ra * op.m * op.RR * op.RL * op.n * op.rd +
+                               (double)op.ra * op.m * op.rc * op.RR * op.rd);
+      const double ba = 8.0 * ((double)op.ra * op.RL * op.rb + (double)op.m * op.RR * op.RL * op.n +
+                               (double)op.rc * op.RR * op.rd + 2.0 * N);
+      const double fl = applies * fa + 8.0 * N * sumj + 6.0 * N * T;
+      const double by = applies * ba + 8.0 * N * (2.0 * sumj + 4.0 * T);
+      g_probe->amend_last(fl, by);
+    }
+  } else {
+    res.method = method;
     const int m = std::max(2, std::min(o.restart, 88));
     double* V = ws.d((int64_t)(m + 1) * N);
     double* r = ws.d(N);
@@ -381,7 +418,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     TT_HIP(hipMemcpyAsync(&h, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
     TT_HIP(hipStreamSynchronize(s));
     res.rel_res = h;
-    if (res.method == 2) res.converged = h <= o.tol * 10.0 || res.converged;
+    if (res.method == 2 || res.method == 4) res.converged = h <= o.tol * 10.0 || res.converged;
   }
   return res;
 }

@@ -1,0 +1,678 @@
+// Restarted GMRES on a local system (PhiL (x) A (x) PhiR) x = f as one
+// persistent cooperative kernel.
+//
+// The unknown x[a][i][c] is split by its left-rank index a: workgroup b owns
+// the slices a in [b * spw, (b + 1) * spw) and with them a contiguous chunk of
+// every Krylov vector.  With the left interface folded into the operator core
+// once per solve,
+//   Q_a[(i, beta'), (b, j)] = sum_beta A[beta, i, j, beta'] PhiL[a, beta, b],
+// a slice of y = (PhiL (x) A (x) PhiR) v is two products that need all of v
+// but nothing another workgroup computes:
+//   T[(i, beta'), d] = sum_{b, j} Q_a[(i, beta'), (b, j)] v[b, j, d]    (T in LDS)
+//   y[a, i, c]       = sum_{beta', d} T[(i, beta'), d] PhiR[c, beta', d]
+// so the operator application runs without grid barriers.  The workgroup's
+// chunk of the Krylov basis stays in LDS for the whole solve; one Arnoldi
+// step (classical Gram-Schmidt, two passes) needs three grid barriers: after
+// the first-pass dots, after the second-pass dots, and after the new direction
+// is published with its norm.  Data crossing workgroups (the published
+// direction, x, and the partial sums) is read with agent-coherent loads, so a
+// barrier only writes back dirty lines and the operator stays cached.  Global
+// sums are formed by every workgroup from per-workgroup partials in the same
+// order, so all workgroups hold bit-equal scalars and take the same branches;
+// the iteration count is bounded by max_iter.
+#include <algorithm>
+#include <cstdlib>
+
+#include "gemm_tile.h"
+#include "krylov.h"
+#include "kernels.h"
+#include "probe.h"
+
+namespace ttnt {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxRestart = 88;
+// LDS staging of the GEMM tiles: A chunks up to 128 rows; B chunks up to 64
+// columns, or a whole K x N right operand of up to kBFull doubles.
+constexpr int kAsDoubles = 16 * (128 + 1);
+constexpr int kBFull = 4096;
+constexpr int kBsDoubles = kBFull;
+
+struct SArgs {
+  const double* phiL;   // [r0][RL][r0]
+  const double* Ap;     // [(i, RR), (RL, j)]
+  const double* phiR;   // [r1][RR][r1]
+  int r0, RL, n, RR, r1;
+  int64_t N;
+  const double* f;
+  double* x;
+  double* W;            // N: current direction, published each step
+  double* Q;            // r0 x (n RR) x (r0 n): folded operator per slice
+  double* Pd1;          // G x (m + 1)
+  double* Pd2;          // G x (m + 1)
+  double* Pn;           // G x 2
+  int m, max_iter, spw, ldv;
+  double tol, eta;
+  unsigned* bar;
+  double* info;         // [iterations, converged, |g_k| / ||f||]
+};
+
+// Grid barrier for a cooperative launch: each wave writes its stores back to
+// the agent coherence point, one thread per workgroup counts in and waits for
+// the epoch.  Readers of data from other workgroups use ld_coherent.
+__device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target) {
+  target += gridDim.x;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+      __builtin_amdgcn_s_sleep(1);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// C = alpha A B for a workgroup-level product, tile shape chosen by N.
+template <bool CohB>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, double alpha, Strided A, Strided B,
+                                        double* C, int64_t cm, int64_t cn, double* As,
+                                        double* Bs) {
+  if (N <= 32) {
+    for (int t = 0; t < cdiv(M, 128); ++t)
+      gemm_tile_pf<128, 32, CohB>(t, 0, M, N, K, alpha, A, B, C, cm, cn, As, Bs);
+  } else {
+    const int tn = cdiv(N, 64);
+    for (int t = 0; t < cdiv(M, 64) * tn; ++t)
+      gemm_tile_pf<64, 64, CohB>(t / tn, t % tn, M, N, K, alpha, A, B, C, cm, cn, As, Bs);
+  }
+  __syncthreads();
+}
+
+// acc[q] += sum_k t[q * K + k] pr[k] over k = part, part + P, ... < K for
+// q < NI (t in LDS, pr in global memory); loads issued U at a time.
+template <int NI>
+__device__ __forceinline__ void row_dots(const double* __restrict__ pr,
+                                         const double* __restrict__ t, int K, int part, int P,
+                                         double* acc) {
+  constexpr int U = 16;
+  int kb = part;
+  for (; kb + P * (U - 1) < K; kb += P * U) {
+    double pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pv[u] = pr[kb + P * u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int q = 0; q < NI; ++q) acc[q] = fma(t[q * K + kb + P * u], pv[u], acc[q]);
+    }
+  }
+  for (; kb < K; kb += P) {
+    const double p = pr[kb];
+#pragma unroll
+    for (int q = 0; q < NI; ++q) acc[q] = fma(t[q * K + kb], p, acc[q]);
+  }
+}
+
+// TM x TN tile of C = alpha A B with A (M x K, row-major, lda) streamed from
+// global memory through As and B (Kp x Np, zero-padded, row stride Np)
+// already in LDS.
+template <int TM, int TN>
+__device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int K, double alpha,
+                                               const double* __restrict__ A, int lda,
+                                               const double* __restrict__ Bl, int Np,
+                                               double* __restrict__ C, int ldc,
+                                               double* __restrict__ As) {
+  constexpr int KC = 16, NA = TM * KC / 256, CG = TN / 4;
+  const int m0 = tm * TM, n0 = tn * TN;
+  const int tid = threadIdx.x, tr = tid / CG, tc = tid % CG;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  double ra[NA];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      const int e = tid + t * 256, mm = e / KC, kk = e % KC;
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[t] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+      const int e = tid + t * 256;
+      As[(e % KC) * (TM + 1) + e / KC] = ra[t];
+    }
+    __syncthreads();
+    if (k0 + KC < K) load(k0 + KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk * (TM + 1) + tr * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bl[(k0 + kk) * Np + n0 + tc + CG * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + tr * 4 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tc + CG * j;
+      if (gn < N) C[(int64_t)gm * ldc + gn] = alpha * acc[i][j];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[4];
+  __shared__ double bcast[4];
+  const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int m = a.m, ldv = a.ldv;
+  const int nr1 = a.n * a.r1, nr0 = a.n * a.r0, nRR = a.n * a.RR;
+  const int a0 = min(a.r0, b * a.spw), a1 = min(a.r0, a0 + a.spw);
+  const int nloc = (a1 - a0) * nr1;
+  const int64_t e0 = (int64_t)a0 * nr1;
+  const int K3 = a.RR * a.r1;
+
+  double* As = lds;
+  double* Bs = As + kAsDoubles;
+  double* Ts = Bs + kBsDoubles;                 // n RR x r1
+  double* Vl = Ts + (int64_t)nRR * a.r1;        // (m + 1) x ldv
+  double* Hpk = Vl + (int64_t)(m + 1) * ldv;    // rotated Hessenberg, column c at c (c + 1) / 2
+  double* hcol = Hpk + m * (m + 1) / 2;
+  double* h2 = hcol + (m + 2);
+  double* cs = h2 + (m + 2);
+  double* sn = cs + (m + 2);
+  double* gv = sn + (m + 2);
+  unsigned target = 0;
+#ifdef KRYLOV_PROF
+  long long pacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long pt = wall_clock64();
+#define PMARK(k) do { if (tid == 0) { const long long t_ = wall_clock64(); pacc[k] += t_ - pt; pt = t_; } } while (0)
+#else
+#define PMARK(k) do { } while (0)
+#endif
+
+  // Q_a for the own slices (once per solve; read back by this workgroup only)
+  for (int s = a0; s < a1; ++s) {
+    double* Qa = a.Q + (int64_t)s * nRR * nr0;
+    for (int j = 0; j < a.n; ++j)
+      wg_gemm<false>(nRR, a.r0, a.RL, 1.0, Strided{a.Ap + j, (int64_t)a.RL * a.n, a.n},
+                     Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1}, Qa + j, nr0, a.n, As,
+                     Bs);
+  }
+
+  // y (own slices) = (PhiL (x) A (x) PhiR)(alpha v) into LDS row `out`; v is
+  // read with coherent loads.
+  // Whole right operand of the first product in LDS when it fits (one round
+  // trip for the coherent loads), else streamed chunk by chunk.
+  const int TNf = a.r1 <= 32 ? 32 : 64;
+  const int Kp = cdiv(nr0, 16) * 16, Np = cdiv(a.r1, TNf) * TNf;
+  const bool fullB = (int64_t)Kp * Np <= kBFull;
+  auto apply = [&](const double* v, double alpha, double* out) {
+    if (fullB) {
+      __syncthreads();
+      for (int e = tid; e < Kp * Np; e += kThreads) {
+        const int k = e / Np, c = e % Np;
+        Bs[e] = (k < nr0 && c < a.r1) ? ld_coherent(v + (int64_t)k * a.r1 + c) : 0.0;
+      }
+      __syncthreads();
+    }
+    for (int s = a0; s < a1; ++s) {
+      const double* Qa = a.Q + (int64_t)s * nRR * nr0;
+      if (fullB) {
+        if (TNf == 32) {
+          for (int t = 0; t < cdiv(nRR, 128); ++t)
+            gemm_tile_ldsb<128, 32>(t, 0, nRR, a.r1, nr0, alpha, Qa, nr0, Bs, Np, Ts, a.r1, As);
+        } else {
+          const int tn = Np / 64;
+          for (int t = 0; t < cdiv(nRR, 64) * tn; ++t)
+            gemm_tile_ldsb<64, 64>(t / tn, t % tn, nRR, a.r1, nr0, alpha, Qa, nr0, Bs, Np, Ts,
+                                   a.r1, As);
+        }
+        __syncthreads();
+      } else {
+        wg_gemm<true>(nRR, a.r1, nr0, alpha, Strided{Qa, nr0, 1}, Strided{v, a.r1, 1}, Ts, a.r1,
+                      1, As, Bs);
+      }
+      PMARK(0);
+      // y[i][c] = sum_k T[i][k] PhiR[c][k]: P lanes per output row c, partial
+      // sums combined across the P lanes by a fixed butterfly.
+      int P = 64;
+      while (P > 1 && P * a.r1 > kThreads) P >>= 1;
+      const int rows = kThreads / P, part = tid % P;
+      double* ys = out + (s - a0) * nr1;
+      for (int c0 = 0; c0 < a.r1; c0 += rows) {
+        const int c = c0 + tid / P;
+        for (int i0 = 0; i0 < a.n; i0 += 4) {
+          const int ni = min(4, a.n - i0);
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          if (c < a.r1) {
+            const double* pr = a.phiR + (int64_t)c * K3;
+            const double* t2 = Ts + (int64_t)i0 * K3;
+            switch (ni) {
+              case 1: row_dots<1>(pr, t2, K3, part, P, acc); break;
+              case 2: row_dots<2>(pr, t2, K3, part, P, acc); break;
+              case 3: row_dots<3>(pr, t2, K3, part, P, acc); break;
+              default: row_dots<4>(pr, t2, K3, part, P, acc); break;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            for (int o = P >> 1; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+          if (part == 0 && c < a.r1) {
+            for (int q = 0; q < ni; ++q) ys[(i0 + q) * a.r1 + c] = acc[q];
+          }
+        }
+      }
+      __syncthreads();
+      PMARK(2);
+    }
+  };
+  // out[i] = <Vl_i, Vl_w> over the chunk for i <= j (gs lanes per vector).
+  auto dots = [&](int j, const double* w, double* out) {
+    int gs = 64;
+    while (gs > 1 && (j + 1) * gs > kThreads) gs >>= 1;
+    const int per = kThreads / gs;
+    for (int i0 = 0; i0 <= j; i0 += per) {
+      const int i = i0 + tid / gs, p = tid % gs;
+      double acc = 0.0;
+      if (i <= j) {
+        const double* vi = Vl + (int64_t)i * ldv;
+        for (int e = p; e < nloc; e += gs) acc = fma(vi[e], w[e], acc);
+      }
+      for (int o = gs >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (p == 0 && i <= j) out[i] = acc;
+    }
+  };
+  // dst[i] = sum over workgroups q of P[q][i], i <= j: gs lanes per i, each
+  // summing every gs-th workgroup with its loads issued together, then a
+  // fixed butterfly; the same order in every workgroup.
+  auto gather = [&](const double* P, int j, double* dst) {
+    int gs = 64;
+    while (gs > 1 && (j + 1) * gs > kThreads) gs >>= 1;
+    const int per = kThreads / gs;
+    for (int i0 = 0; i0 <= j; i0 += per) {
+      const int i = i0 + tid / gs, p = tid % gs;
+      double acc = 0.0;
+      if (i <= j) {
+        constexpr int U = 8;
+        for (int q0 = p; q0 < G; q0 += gs * U) {
+          double v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = q0 + gs * u;
+            v[u] = q < G ? ld_coherent(P + (int64_t)q * (m + 1) + i) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc += v[u];
+        }
+      }
+      for (int o = gs >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (p == 0 && i <= j) dst[i] = acc;
+    }
+    __syncthreads();
+  };
+  // sum over workgroups of Pn[2 q + k] by wave 0 (fixed order), into bcast[k]
+  auto gather_pn = [&](int k) {
+    if (tid < 64) {
+      double acc = 0.0;
+      for (int q = lane; q < G; q += 64) acc += ld_coherent(a.Pn + 2 * q + k);
+      acc = wave_sum(acc);
+      if (lane == 0) bcast[2 + k] = acc;
+    }
+  };
+  // w -= sum_i h[i] Vl_i over the chunk; returns this thread's ||w||^2 share
+  auto orth = [&](double* w, int j, const double* h) {
+    double nn = 0.0;
+    for (int e = tid; e < nloc; e += kThreads) {
+      double s0 = w[e], s1 = 0.0;
+      int i = 0;
+      for (; i + 1 <= j; i += 2) {
+        s0 -= h[i] * Vl[(int64_t)i * ldv + e];
+        s1 -= h[i + 1] * Vl[(int64_t)(i + 1) * ldv + e];
+      }
+      if (i <= j) s0 -= h[i] * Vl[(int64_t)i * ldv + e];
+      const double r = s0 + s1;
+      w[e] = r;
+      nn = fma(r, r, nn);
+    }
+    return nn;
+  };
+
+  int total = 0;
+  bool conv = false;
+  double fnorm = 0.0, tgt = -1.0, res_est = 0.0;
+  while (true) {
+    // r = f - A x into Vl_0 and W (unnormalised), ||r||^2 and ||f||^2
+    apply(a.x, 1.0, Vl);
+    double rr = 0.0, ff = 0.0;
+    for (int e = tid; e < nloc; e += kThreads) {
+      const double fe = a.f[e0 + e];
+      const double r = fe - Vl[e];
+      Vl[e] = r;
+      a.W[e0 + e] = r;
+      rr = fma(r, r, rr);
+      ff = fma(fe, fe, ff);
+    }
+    rr = wg_sum(rr, red);
+    ff = wg_sum(ff, red);
+    if (tid == 0) {
+      a.Pn[2 * b] = rr;
+      a.Pn[2 * b + 1] = ff;
+    }
+    grid_sync(a.bar, target);
+    gather_pn(0);
+    __syncthreads();
+    gather_pn(1);
+    __syncthreads();
+    const double beta = sqrt(bcast[2]);
+    if (tgt < 0.0) {
+      fnorm = sqrt(bcast[3]);
+      tgt = fmax(a.tol * fnorm, a.eta * beta);
+    }
+    if (fnorm == 0.0) {
+      for (int e = tid; e < nloc; e += kThreads) a.x[e0 + e] = 0.0;
+      conv = true;
+      res_est = 0.0;
+      break;
+    }
+    res_est = beta;
+    if (beta <= tgt || total >= a.max_iter) {
+      conv = beta <= tgt;
+      break;
+    }
+    for (int i = tid; i < m + 2; i += kThreads) gv[i] = i == 0 ? beta : 0.0;
+    __syncthreads();
+    double nu = beta;
+    int j = 0;
+    while (true) {
+      double* w = Vl + (int64_t)(j + 1) * ldv;
+      apply(a.W, 1.0 / nu, w);
+      // normalise V_j (its norm is known now), first-pass dots
+      {
+        const double inv = 1.0 / nu;
+        double* vj = Vl + (int64_t)j * ldv;
+        for (int e = tid; e < nloc; e += kThreads) vj[e] *= inv;
+        __syncthreads();
+        dots(j, w, a.Pd1 + (int64_t)b * (m + 1));
+      }
+      PMARK(3);
+      grid_sync(a.bar, target);
+      PMARK(4);
+      gather(a.Pd1, j, hcol);
+      orth(w, j, hcol);
+      __syncthreads();
+      dots(j, w, a.Pd2 + (int64_t)b * (m + 1));
+      PMARK(5);
+      grid_sync(a.bar, target);
+      PMARK(4);
+      gather(a.Pd2, j, h2);
+      {
+        double nn = orth(w, j, h2);
+        for (int i = tid; i <= j; i += kThreads) hcol[i] += h2[i];
+        for (int e = tid; e < nloc; e += kThreads) a.W[e0 + e] = w[e];
+        nn = wg_sum(nn, red);
+        if (tid == 0) a.Pn[2 * b] = nn;
+      }
+      PMARK(5);
+      grid_sync(a.bar, target);
+      PMARK(4);
+      gather_pn(0);
+      __syncthreads();
+      // norm, Hessenberg column, Givens rotation (every workgroup, same order)
+      if (tid == 0) {
+        const double nrm = sqrt(bcast[2]);
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+          hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+          hcol[i] = t;
+        }
+        const double p = hcol[j], q = nrm;
+        const double rho = sqrt(p * p + q * q);
+        const double c = rho > 0.0 ? p / rho : 1.0, sg = rho > 0.0 ? q / rho : 0.0;
+        cs[j] = c;
+        sn[j] = sg;
+        hcol[j] = rho;
+        gv[j + 1] = -sg * gv[j];
+        gv[j] = c * gv[j];
+        double* col = Hpk + j * (j + 1) / 2;
+        for (int i = 0; i <= j; ++i) col[i] = hcol[i];
+        bcast[0] = nrm;
+        bcast[1] = fabs(gv[j + 1]);
+      }
+      __syncthreads();
+      PMARK(6);
+      nu = bcast[0];
+      res_est = bcast[1];
+      ++j;
+      ++total;
+      if (res_est <= tgt) {
+        conv = true;
+        break;
+      }
+      if (j >= m || total >= a.max_iter || !(nu > 0.0)) break;
+    }
+    // y = R^{-1} g by one wave (lanes hold rows r and r + 64), then x += V y
+    if (tid < 64) {
+      double g0 = lane < j ? gv[lane] : 0.0;
+      double g1 = lane + 64 < j ? gv[lane + 64] : 0.0;
+      for (int i = j - 1; i >= 0; --i) {
+        const double gi = __shfl(i < 64 ? g0 : g1, i & 63, 64);
+        const double* col = Hpk + i * (i + 1) / 2;
+        const double d = col[i];
+        const double yi = d != 0.0 ? gi / d : 0.0;
+        if (lane == 0) h2[i] = yi;
+        if (lane < i) g0 -= col[lane] * yi;
+        if (lane + 64 < i) g1 -= col[lane + 64] * yi;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nloc; e += kThreads) {
+      double acc = a.x[e0 + e];
+      for (int i = 0; i < j; ++i) acc = fma(h2[i], Vl[(int64_t)i * ldv + e], acc);
+      a.x[e0 + e] = acc;
+    }
+    if (conv || total >= a.max_iter) break;
+    grid_sync(a.bar, target);
+  }
+#ifdef KRYLOV_PROF
+  if (b == 0 && tid == 0)
+    for (int k = 0; k < 8; ++k) a.info[3 + k] = (double)pacc[k] * 10.0;   // ns at 100 MHz
+#endif
+  if (b == 0 && tid == 0) {
+    a.info[0] = (double)total;
+    a.info[1] = conv ? 1.0 : 0.0;
+    a.info[2] = fnorm > 0.0 ? res_est / fnorm : 0.0;
+  }
+}
+
+struct DevInfo {
+  int device = -1;
+  int cus = 0;
+  int lds_max = 0;
+};
+
+const DevInfo& dev_info() {
+  thread_local DevInfo di;
+  int dev = 0;
+  TT_HIP(hipGetDevice(&dev));
+  if (di.device != dev) {
+    TT_HIP(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int coop = 0;
+    TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    TT_REQUIRE(coop != 0, "device does not support cooperative launches");
+    TT_HIP(hipDeviceGetAttribute(&di.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    di.device = dev;
+  }
+  return di;
+}
+
+int grid_cap() {
+  static const int want = [] {
+    const char* e = std::getenv("TTNT_KRYLOV_GRID");
+    const int v = e ? std::atoi(e) : 0;
+    return v > 0 ? v : kKrylovMaxGrid;
+  }();
+  return want;
+}
+
+struct Plan {
+  int G = 0, spw = 0, m = 0, ldv = 0;
+  size_t lds_bytes = 0;
+};
+
+size_t lds_doubles(const KrylovShape& sh, int m, int ldv) {
+  return (size_t)kAsDoubles + kBsDoubles + (size_t)sh.n * sh.RR * sh.r1 + (size_t)(m + 1) * ldv +
+         (size_t)m * (m + 1) / 2 + 5 * (size_t)(m + 2) + 32;
+}
+
+// Workgroups, slices per workgroup and the restart length that fits in LDS
+// (the largest m <= restart, at least 2); G == 0 when nothing fits.
+Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes) {
+  Plan p;
+  const int cap = std::max(1, grid_cap());
+  p.spw = (sh.r0 + cap - 1) / cap;
+  p.G = (sh.r0 + p.spw - 1) / p.spw;
+  const int nloc = p.spw * sh.n * sh.r1;
+  p.ldv = nloc + ((nloc % 2 == 0) ? 1 : 0);
+  const size_t limit = (size_t)std::max(0, lds_limit_bytes - 1024) / sizeof(double);
+  int m = std::min(restart, kMaxRestart);
+  while (m >= 2 && lds_doubles(sh, m, p.ldv) > limit) --m;
+  if (m < 2) {
+    p.G = 0;
+    return p;
+  }
+  p.m = m;
+  p.lds_bytes = lds_doubles(sh, m, p.ldv) * sizeof(double);
+  return p;
+}
+
+}  // namespace
+
+bool krylov_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("TTNT_KRYLOV");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+int krylov_grid() { return grid_cap(); }
+
+bool krylov_fits(const KrylovShape& sh, int restart) {
+  if (restart < 2 || sh.r0 <= 0 || sh.r1 <= 0 || sh.n <= 0 || sh.RL <= 0 || sh.RR <= 0)
+    return false;
+  return make_plan(sh, restart, dev_info().lds_max).G > 0;
+}
+
+size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
+  const int64_t N = (int64_t)sh.r0 * sh.n * sh.r1;
+  const int cap = std::max(1, grid_cap());
+  const int spw = (sh.r0 + cap - 1) / cap;
+  const int64_t G = (sh.r0 + spw - 1) / spw;
+  const int64_t m = std::min(restart, kMaxRestart);
+  int64_t need = 0;
+  need += N + 32;                                                  // W
+  need += (int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n + 32;       // Q
+  need += 2 * (G * (m + 1) + 32);                    // Pd1, Pd2
+  need += 2 * G + 32;                                // Pn
+  need += 64;                                        // barrier counter
+  return (size_t)need + 8 * 32;
+}
+
+bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, const double* Ap,
+                  const double* phiR, const double* f, double* x, int restart, int max_iter,
+                  double tol, double eta, double* ws, size_t ws_doubles, double* info,
+                  int /*grid*/) {
+  TT_REQUIRE(max_iter >= 0, "Krylov solve: negative iteration limit");
+  const DevInfo& di = dev_info();
+  const Plan p = make_plan(sh, restart, di.lds_max);
+  TT_REQUIRE(p.G > 0, "Krylov solve: local system too large for the LDS-resident basis");
+  TT_REQUIRE(ws_doubles >= krylov_ws_doubles(sh, restart, 0), "Krylov solve: workspace too small");
+  const int64_t N = (int64_t)sh.r0 * sh.n * sh.r1;
+  double* cur = ws;
+  auto take = [&](int64_t count) {
+    double* r = cur;
+    cur += (count + 31) / 32 * 32;
+    return r;
+  };
+  SArgs a;
+  a.phiL = phiL;
+  a.Ap = Ap;
+  a.phiR = phiR;
+  a.r0 = sh.r0;
+  a.RL = sh.RL;
+  a.n = sh.n;
+  a.RR = sh.RR;
+  a.r1 = sh.r1;
+  a.N = N;
+  a.f = f;
+  a.x = x;
+  a.W = take(N);
+  a.Q = take((int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n);
+  a.Pd1 = take((int64_t)p.G * (p.m + 1));
+  a.Pd2 = take((int64_t)p.G * (p.m + 1));
+  a.Pn = take(2 * (int64_t)p.G);
+  double* barslot = take(8);
+  a.bar = reinterpret_cast<unsigned*>(barslot);
+  a.m = p.m;
+  a.max_iter = max_iter;
+  a.spw = p.spw;
+  a.ldv = p.ldv;
+  a.tol = tol;
+  a.eta = eta;
+  a.info = info;
+  TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
+
+  static thread_local int attr_bytes = -1;
+  if (attr_bytes < (int)p.lds_bytes) {
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(gmres_slices_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, di.lds_max - 1024));
+    attr_bytes = di.lds_max - 1024;
+  }
+  int per_cu = 0;
+  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(gmres_slices_kernel), kThreads, p.lds_bytes));
+  TT_REQUIRE((int64_t)per_cu * di.cus >= p.G, "Krylov solve: grid exceeds co-resident capacity");
+
+  fill(s, barslot, 1, 0.0);
+  ++g_launches;
+  hipEvent_t pe = nullptr;
+  if (g_probe) pe = g_probe->begin(s, kProbeKrylov, 0.0, 0.0);   // work amended after the run
+  void* args[] = {&a};
+  TT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gmres_slices_kernel),
+                                    dim3(p.G), dim3(kThreads), args, p.lds_bytes, s));
+  if (pe) g_probe->end(s);
+  return pe != nullptr;
+}
+
+int krylov_restart(const KrylovShape& sh, int restart) {
+  const Plan p = make_plan(sh, restart, dev_info().lds_max);
+  return p.G > 0 ? p.m : 0;
+}
+
+}  // namespace ttnt

@@ -7,7 +7,7 @@ namespace ttnt {
 
 // Kernel classes timed by the probe.
 enum ProbeClass { kProbeGemmNN = 0, kProbeGemmTN, kProbeGemmNT, kProbeGemmTT, kProbeArnoldi,
-                  kProbeMatvec, kProbeClasses };
+                  kProbeMatvec, kProbeKrylov, kProbeClasses };
 
 struct Probe {
   bool active = false;
@@ -27,6 +27,9 @@ struct Probe {
   // Returns the start event to record before a launch of class c, or nullptr.
   hipEvent_t begin(hipStream_t s, int c, double flops, double bytes);
   void end(hipStream_t s);
+  // Replaces the work recorded for the most recent bracket (for launches whose
+  // work is known only after they ran).
+  void amend_last(double flops, double bytes);
   // Waits for the window's events and folds them into the totals.
   void close();
   void reset();

@@ -51,6 +51,12 @@ void Probe::end(hipStream_t s) {
   ++used;
 }
 
+void Probe::amend_last(double f, double b) {
+  if (used == 0) return;
+  flops[used - 1] = f;
+  bytes[used - 1] = b;
+}
+
 void Probe::calibrate(hipStream_t s) {
   // empty brackets queued behind a hold: the event pair's own interval
   if (ev.empty()) begin(s, 0, 0.0, 0.0), end(s), used = 0;

@@ -89,7 +89,7 @@ class TTProbeStats(ctypes.Structure):
 
 
 PROBE_CLASSES = {0: "gemm_nn", 1: "gemm_tn", 2: "gemm_nt", 3: "gemm_tt", 4: "arnoldi",
-                 5: "core_matvec"}
+                 5: "core_matvec", 6: "krylov"}
 
 
 class TTStepInfo(ctypes.Structure):
