@@ -48,6 +48,8 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-probe", action="store_true")
+    p.add_argument("--ttk-steps", type=int, default=60,
+                   help="step limit of the time-to-k run (0 skips it)")
     return p.parse_args()
 
 
@@ -71,6 +73,43 @@ def _cpu_baseline(wl, seconds: float):
     return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
                 sample=f"{steps} exact sweep power steps of the same workload "
                        f"({prob.n_unknowns} unknowns) in {dt:.1f} s")
+
+
+def _time_to_k(wl, rmax, rhs_mode, max_steps, rel=1e-5):
+    """Wall time from the first step of a fresh solver until k stays within
+    `rel` of the converged k of the same FP64 iteration (the last k when
+    |dk| < tol_k, else the last k of the run, flagged unconverged)."""
+    import torch
+    from paper_2309_03347_amd.solver import KeffSolver
+    s = KeffSolver(wl, rmax=rmax, rhs_mode=rhs_mode)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times, ks = [], []
+    converged = False
+    for _ in range(max_steps):
+        rec = s.step()
+        times.append(time.perf_counter() - t0)
+        ks.append(rec.k)
+        if abs(rec.dk) < wl.tol_k:
+            converged = True
+            break
+    s.close()
+    k_ref = ks[-1]
+    hit = None
+    for i in range(len(ks)):
+        if all(abs(k - k_ref) <= rel * abs(k_ref) for k in ks[i:]):
+            hit = i
+            break
+    tail = ks[-10:]
+    out = dict(rel=rel, k_ref=k_ref, converged=converged, steps=len(ks),
+               tail_rel_spread=(max(tail) - min(tail)) / abs(k_ref))
+    # A k that is still drifting by more than `rel` per step has no meaningful
+    # time-to-k: report null with the observed spread.
+    if hit is not None and (converged or out["tail_rel_spread"] <= rel):
+        out.update(seconds=times[hit], step=hit + 1)
+    else:
+        out.update(seconds=None, step=None)
+    return out
 
 
 def main():
@@ -111,7 +150,10 @@ def main():
         # dominant kernel class by total device time
         name, st = max(probe.items(), key=lambda kv: kv[1]["total_ms"])
         avg_ms = st["total_ms"] / max(1, st["launches"])
-        if name.startswith("gemm"):
+        # bound by arithmetic intensity against the FP64 ridge (peak flops / HBM bandwidth)
+        ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+        intensity = st["flops"] / max(1.0, st["bytes"])
+        if intensity >= ridge:
             achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
             roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                             frac=achieved / PEAK_FP64_TFLOPS, traffic=None)
@@ -119,9 +161,14 @@ def main():
             achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
             roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                             frac=achieved / PEAK_HBM_GBS, traffic=None)
-        roofline.update(kernel=name, launches=st["launches"], avg_us=avg_ms * 1e3,
+        roofline.update(kernel=name, intensity_flop_per_byte=intensity,
+                        launches=st["launches"], avg_us=avg_ms * 1e3,
                         flops_per_launch=st["flops"] / max(1, st["launches"]),
                         bytes_per_launch=st["bytes"] / max(1, st["launches"]))
+
+    ttk = None
+    if args.ttk_steps > 0:
+        ttk = _time_to_k(wl, rmax, args.rhs_mode, args.ttk_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -149,6 +196,7 @@ def main():
         "sweeps_last": hist[-1].sweeps,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "time_to_k": ttk,
     }
     if probe is not None:
         out["kernel_probe"] = {k: dict(launches=v["launches"], ms=round(v["total_ms"], 3))

@@ -331,12 +331,395 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
     for (int e = tid; e < N; e += nt) bg[e] = b[e];
 }
 
+// ---------------------------------------------------------------------------
+// LDS-resident factorizations, one workgroup of 256 threads (4 wavefronts).
+// Matrices are held column-major with an odd leading dimension so that lanes
+// walking different columns at the same row hit different banks.
+// ---------------------------------------------------------------------------
+constexpr int WS = 256;
+
+__host__ __device__ __forceinline__ int odd_ld(int m) { return m | 1; }
+
+// Rows [j + 1, m) split into four contiguous segments, one per wavefront.
+__device__ __forceinline__ void row_segment(int j, int m, int w, int& r0, int& r1) {
+  const int len = m - j - 1;
+  const int seg = len > 0 ? (len + 3) / 4 : 0;
+  r0 = j + 1 + w * seg;
+  r1 = min(m, r0 + seg);
+}
+
+// sum_{r in [r0, r1)} x[r] y[r] + init, LDS operands loaded eight at a time.
+__device__ __forceinline__ double seg_dot(const double* x, const double* y, int r0, int r1,
+                                          double init) {
+  double p[4] = {init, 0.0, 0.0, 0.0};
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = x[r + u];
+      b[u] = y[r + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u & 3] = fma(a[u], b[u], p[u & 3]);
+  }
+  for (; r < r1; ++r) p[0] = fma(x[r], y[r], p[0]);
+  return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// y[r] += alpha x[r] for r in [r0, r1), eight rows at a time.
+__device__ __forceinline__ void seg_axpy(double alpha, const double* x, double* y, int r0,
+                                         int r1) {
+  int r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = x[r + u];
+      b[u] = y[r + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[r + u] = fma(alpha, a[u], b[u]);
+  }
+  for (; r < r1; ++r) y[r] = fma(alpha, x[r], y[r]);
+}
+
+// Householder QR of the column-major m x n matrix A (leading dimension ld):
+// the upper triangle receives R, the part below the diagonal the reflector
+// vectors (unit leading entry implicit), tau[j] the factors of
+// H_j = I - tau_j v_j v_j^T.  pw is LDS scratch of 4 * (n + 1) doubles.
+__device__ void hh_qr(double* A, int m, int n, int ld, double* tau, double* pw) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = min(m, n);
+  for (int j = 0; j < k; ++j) {
+    double* aj = A + (int64_t)j * ld;
+    int r0, r1;
+    row_segment(j, m, w, r0, r1);
+    double s = 0.0;
+    for (int r = r0 + lane; r < r1; r += 64) s = fma(aj[r], aj[r], s);
+    s = wave_sum(s);
+    if (lane == 0) pw[w] = s;
+    __syncthreads();
+    const double nrm2 = (pw[0] + pw[1]) + (pw[2] + pw[3]);
+    const double alpha = aj[j];
+    double t = 0.0, beta = alpha, inv = 0.0;
+    if (nrm2 > 0.0) {
+      const double sigma = sqrt(alpha * alpha + nrm2);
+      beta = alpha >= 0.0 ? -sigma : sigma;
+      t = (beta - alpha) / beta;
+      inv = 1.0 / (alpha - beta);
+    }
+    for (int r = r0 + lane; r < r1; r += 64) aj[r] *= inv;
+    __syncthreads();
+    if (tid == 0) {
+      aj[j] = beta;
+      tau[j] = t;
+    }
+    if (t != 0.0) {
+      // partial w_c over this wavefront's rows
+      for (int c = j + 1 + lane; c < n; c += 64) {
+        const double* ac = A + (int64_t)c * ld;
+        pw[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, w == 0 ? ac[j] : 0.0);
+      }
+      __syncthreads();
+      for (int c = j + 1 + lane; c < n; c += 64) {
+        double* ac = A + (int64_t)c * ld;
+        const double wc = t * ((pw[c] + pw[(n + 1) + c]) +
+                               (pw[2 * (n + 1) + c] + pw[3 * (n + 1) + c]));
+        seg_axpy(-wc, aj, ac, r0, r1);
+        if (w == 0) ac[j] -= wc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Overwrites the reflector storage of hh_qr with the first k = min(m, n)
+// columns of Q = H_0 ... H_{k-1} [I_k; 0].  R must have been copied out.
+__device__ void hh_form_q(double* A, int m, int n, int ld, const double* tau, double* pw) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = min(m, n);
+  for (int j = k - 1; j >= 0; --j) {
+    double* aj = A + (int64_t)j * ld;
+    const double t = tau[j];
+    int r0, r1;
+    row_segment(j, m, w, r0, r1);
+    if (t != 0.0) {
+      for (int c = j + 1 + lane; c < k; c += 64) {
+        const double* ac = A + (int64_t)c * ld;
+        pw[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, w == 0 ? ac[j] : 0.0);
+      }
+    }
+    __syncthreads();
+    if (t != 0.0) {
+      for (int c = j + 1 + lane; c < k; c += 64) {
+        double* ac = A + (int64_t)c * ld;
+        const double wc = t * ((pw[c] + pw[(n + 1) + c]) +
+                               (pw[2 * (n + 1) + c] + pw[3 * (n + 1) + c]));
+        seg_axpy(-wc, aj, ac, r0, r1);
+        if (w == 0) ac[j] -= wc;
+      }
+    }
+    __syncthreads();
+    // column j of Q: (1 - t) e_j - t v_j
+    for (int r = r0 + lane; r < r1; r += 64) aj[r] *= -t;
+    if (tid == 0) aj[j] = 1.0 - t;
+    for (int r = tid; r < j; r += WS) aj[r] = 0.0;
+    __syncthreads();
+  }
+}
+
+// QR with diag(R) >= 0: Q (m x k), R (k x n), k = min(m, n); A row-major.
+__global__ __launch_bounds__(WS) void qr_lds_kernel(const double* __restrict__ Ag, int m, int n,
+                                                    int ldag, double* __restrict__ Qg, int ldq,
+                                                    double* __restrict__ R, int ldr) {
+  extern __shared__ double sm[];
+  const int ld = odd_ld(m), k = min(m, n), tid = threadIdx.x;
+  double* A = sm;
+  double* tau = A + (int64_t)ld * n;
+  double* sg = tau + k;
+  double* pw = sg + k;
+  for (int e = tid; e < m * n; e += WS) {
+    const int i = e / n, c = e % n;
+    A[(int64_t)c * ld + i] = Ag[(int64_t)i * ldag + c];
+  }
+  __syncthreads();
+  hh_qr(A, m, n, ld, tau, pw);
+  for (int i = tid; i < k; i += WS) sg[i] = A[(int64_t)i * ld + i] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  for (int e = tid; e < k * n; e += WS) {
+    const int i = e / n, c = e % n;
+    R[(int64_t)i * ldr + c] = c >= i ? sg[i] * A[(int64_t)c * ld + i] : 0.0;
+  }
+  __syncthreads();
+  hh_form_q(A, m, n, ld, tau, pw);
+  for (int e = tid; e < m * k; e += WS) {
+    const int i = e / k, c = e % k;
+    Qg[(int64_t)i * ldq + c] = sg[c] * A[(int64_t)c * ld + i];
+  }
+}
+
+// One DPP lane exchange of a double (two 32-bit moves).
+template <int Ctrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, Ctrl, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, Ctrl, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over aligned groups of Lp lanes.  Every exchange pairs lanes by an
+// involution (xor 1, xor 2, mirror within 8, mirror within 16, then xor 16
+// and xor 32), so all lanes of a group hold the bit-identical sum.
+__device__ __forceinline__ double group_sum(double v, int Lp) {
+  if (Lp >= 2) v += dpp_move<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+  if (Lp >= 4) v += dpp_move<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+  if (Lp >= 8) v += dpp_move<0x141>(v);    // row_half_mirror
+  if (Lp >= 16) v += dpp_move<0x140>(v);   // row_mirror
+  if (Lp >= 32) v += __shfl_xor(v, 16, 64);
+  if (Lp >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Thin SVD G = U S V^T (m >= n), G row-major.  Householder QR G = Q R, then
+// one-sided Jacobi on R^T: R^T W = Y with orthogonal columns, so that
+// U = Q W and V = Y diag(1 / |Y_j|).  Singular values sorted descending;
+// each column of U has its largest-magnitude entry positive.
+__global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ Gg, int m, int n,
+                                                     int ldg, double* __restrict__ U, int ldu,
+                                                     double* __restrict__ S,
+                                                     double* __restrict__ V, int ldv) {
+  extern __shared__ double sm[];
+  __shared__ int s_rot;
+  __shared__ double s_fro;
+  const int ld = odd_ld(m), ldn = odd_ld(n), tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double* A = sm;                               // ld x n
+  double* Y = A + (int64_t)ld * n;              // ldn x n
+  double* Wm = Y + (int64_t)ldn * n;            // ldn x n
+  double* tau = Wm + (int64_t)ldn * n;          // n
+  double* sig = tau + n;                        // n
+  double* rk = sig + n;                         // n
+  double* pw = rk + n;                          // 4 (n + 1)
+  for (int e = tid; e < m * n; e += WS) {
+    const int i = e / n, c = e % n;
+    A[(int64_t)c * ld + i] = Gg[(int64_t)i * ldg + c];
+  }
+  __syncthreads();
+  hh_qr(A, m, n, ld, tau, pw);
+  // Y = R^T (column c of Y is row c of R), W = I
+  for (int e = tid; e < n * n; e += WS) {
+    const int c = e / n, r = e % n;
+    Y[(int64_t)c * ldn + r] = c <= r ? A[(int64_t)r * ld + c] : 0.0;
+    Wm[(int64_t)c * ldn + r] = c == r ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  hh_form_q(A, m, n, ld, tau, pw);
+  // Frobenius norm of R: columns whose norm is below eps * ||G||_F are zero
+  if (w == 0) {
+    double f = 0.0;
+    for (int e = lane; e < n * n; e += 64) {
+      const double x = Y[(int64_t)(e / n) * ldn + e % n];
+      f = fma(x, x, f);
+    }
+    f = wave_sum(f);
+    if (lane == 0) s_fro = f;
+  }
+  __syncthreads();
+  const double sfmin = s_fro * (2.3e-16 * 2.3e-16);
+  const double tol = 1e-15;
+  const int np = n + (n & 1), npair = np / 2;
+  int Lp = 64;
+  while (Lp > 1 && npair * Lp > WS) Lp >>= 1;
+  const int g = tid / Lp, l = tid % Lp;
+  for (int sweep = 0; sweep < 60 && np > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      int p = 0, q = 0;
+      bool valid = false;
+      if (g < npair) {
+        p = rr_player(g, round, np);
+        q = rr_player(np - 1 - g, round, np);
+        if (p > q) { const int tq = p; p = q; q = tq; }
+        valid = q < n;
+      }
+      double a = 0.0, b = 0.0, gg = 0.0;
+      double* yp = Y + (int64_t)p * ldn;
+      double* yq = Y + (int64_t)q * ldn;
+      if (valid) {
+        for (int e = l; e < n; e += Lp) {
+          const double x = yp[e], y = yq[e];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          gg = fma(x, y, gg);
+        }
+      }
+      a = group_sum(a, Lp);
+      b = group_sum(b, Lp);
+      gg = group_sum(gg, Lp);
+      if (valid && gg != 0.0 && fabs(gg) > tol * sqrt(a * b) && a > sfmin && b > sfmin) {
+        const double zeta = (b - a) / (2.0 * gg);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        double* wp = Wm + (int64_t)p * ldn;
+        double* wq = Wm + (int64_t)q * ldn;
+        for (int e = l; e < n; e += Lp) {
+          const double x = yp[e], y = yq[e];
+          yp[e] = c * x - sn * y;
+          yq[e] = sn * x + c * y;
+          const double u = wp[e], v = wq[e];
+          wp[e] = c * u - sn * v;
+          wq[e] = sn * u + c * v;
+        }
+        if (l == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rot = s_rot;
+    __syncthreads();
+    if (rot == 0) break;
+  }
+  // singular values and their descending order
+  for (int c = w; c < n; c += 4) {
+    double a = 0.0;
+    for (int e = lane; e < n; e += 64) a = fma(Y[(int64_t)c * ldn + e], Y[(int64_t)c * ldn + e], a);
+    a = wave_sum(a);
+    if (lane == 0) sig[c] = sqrt(a);
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += WS) {
+    int r = 0;
+    const double sp = sig[p];
+    for (int q = 0; q < n; ++q) r += (sig[q] > sp) || (sig[q] == sp && q < p);
+    rk[p] = (double)r;
+  }
+  __syncthreads();
+  // U(:, j) = Q W(:, j) with the sign gauge, V(:, j) = Y(:, j) / sigma_j
+  for (int c = w; c < n; c += 4) {
+    const int j = (int)rk[c];
+    const double sp = sig[c];
+    const double* wc = Wm + (int64_t)c * ldn;
+    double uv[4];
+    double best = -1.0, sgn = 1.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = lane + 64 * t;
+      double acc = 0.0;
+      if (i < m)
+        for (int kk = 0; kk < n; ++kk) acc = fma(A[(int64_t)kk * ld + i], wc[kk], acc);
+      uv[t] = acc;
+      if (i < m && fabs(acc) > best) { best = fabs(acc); sgn = acc < 0.0 ? -1.0 : 1.0; bi = i; }
+    }
+    for (int i0 = 256; i0 < m; i0 += 64) {
+      const int i = i0 + lane;
+      if (i < m) {
+        double acc = 0.0;
+        for (int kk = 0; kk < n; ++kk) acc = fma(A[(int64_t)kk * ld + i], wc[kk], acc);
+        if (fabs(acc) > best) { best = fabs(acc); sgn = acc < 0.0 ? -1.0 : 1.0; bi = i; }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const double os = __shfl_xor(sgn, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; sgn = os; bi = oi; }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = lane + 64 * t;
+      if (i < m) U[(int64_t)i * ldu + j] = sgn * uv[t];
+    }
+    for (int i0 = 256; i0 < m; i0 += 64) {
+      const int i = i0 + lane;
+      if (i < m) {
+        double acc = 0.0;
+        for (int kk = 0; kk < n; ++kk) acc = fma(A[(int64_t)kk * ld + i], wc[kk], acc);
+        U[(int64_t)i * ldu + j] = sgn * acc;
+      }
+    }
+    const double inv = sp > 0.0 ? sgn / sp : 0.0;
+    for (int e = lane; e < n; e += 64) V[(int64_t)e * ldv + j] = Y[(int64_t)c * ldn + e] * inv;
+    if (lane == 0) S[j] = sp;
+  }
+}
+
+size_t qr_lds_doubles(int m, int n) {
+  return (size_t)odd_ld(m) * n + 2 * (size_t)std::min(m, n) + 4 * ((size_t)n + 1) + 8;
+}
+size_t svd_lds_doubles(int m, int n) {
+  return (size_t)odd_ld(m) * n + 2 * (size_t)odd_ld(n) * n + 3 * (size_t)n +
+         4 * ((size_t)n + 1) + 8;
+}
+
+// Largest dynamic LDS allocation of one workgroup on the current device (bytes).
+int lds_limit() {
+  thread_local int dev = -1, lim = 0;
+  int d = 0;
+  TT_HIP(hipGetDevice(&d));
+  if (d != dev) {
+    TT_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, d));
+    lim -= 1024;
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(qr_lds_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_lds_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    dev = d;
+  }
+  return lim;
+}
+
 }  // namespace
 
 void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R, int ldr,
         double* tau) {
   if (m <= 0 || n <= 0) return;
   ++g_launches;
+  if (qr_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
+    qr_lds_kernel<<<1, WS, qr_lds_doubles(m, n) * 8, s>>>(A, m, n, lda, Q, ldq, R, ldr);
+    TT_HIP(hipGetLastError());
+    return;
+  }
   const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
   qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
       A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
@@ -350,6 +733,11 @@ void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, do
   if (m <= 0 || n <= 0) return;
   TT_REQUIRE(m >= n, "svd expects m >= n");
   ++g_launches;
+  if (svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
+    svd_lds_kernel<<<1, WS, svd_lds_doubles(m, n) * 8, s>>>(G, m, n, ldg, U, ldu, S, V, ldv);
+    TT_HIP(hipGetLastError());
+    return;
+  }
   const size_t need = svd_work_doubles(m, n);
   const bool lds = need <= (size_t)kLdsDoubles;
   svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
