@@ -34,6 +34,8 @@ WORKLOADS = {
                             "32^3 nodes, 4 groups, S4 (24 dirs), two-region, rank cap 32, tol 1e-8"),
     "homogeneous_n8_S2": (lambda W: W.config(0),
                           "8^3 nodes, 1 group, S2 (8 dirs), homogeneous, rank cap 8, tol 1e-10"),
+    "batch256_uneven": (None, "256 independent instances: 16^3-64^3 nodes, 1-8 groups, S2-S8, "
+                              "rank caps 4-48, tol 1e-6; one batched step advances all"),
 }
 
 
@@ -48,6 +50,10 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-probe", action="store_true")
+    p.add_argument("--streams", type=int, default=8, help="streams of the batched workload")
+    p.add_argument("--build-workers", type=int, default=1,
+                   help="host processes building the batched workload's operators")
+    p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
     p.add_argument("--ttk-steps", type=int, default=60,
                    help="step limit of the time-to-k run (0 skips it)")
     return p.parse_args()
@@ -112,12 +118,85 @@ def _time_to_k(wl, rmax, rhs_mode, max_steps, rel=1e-5):
     return out
 
 
+def _build_ops(w):
+    from paper_2309_03347_amd import operators
+    return operators.build(w)
+
+
+def _bench_batch(args):
+    """Many uneven instances advanced by tt_power_step_batched."""
+    import concurrent.futures as cf
+    import torch
+    from paper_2309_03347_amd import workload as W
+    from paper_2309_03347_amd.solver import KeffSolver, step_batched
+    wls = W.batch_instances(args.instances)
+    t0 = time.perf_counter()
+    if args.build_workers > 1:
+        with cf.ProcessPoolExecutor(max_workers=args.build_workers) as ex:
+            ops = list(ex.map(_build_ops, wls, chunksize=4))
+    else:
+        ops = [_build_ops(w) for w in wls]
+    t_ops = time.perf_counter() - t0
+    print(f"operators built for {len(wls)} instances in {t_ops:.1f} s", file=sys.stderr, flush=True)
+    solvers = [KeffSolver(w, rmax=w.rmax, ops=o) for w, o in zip(wls, ops)]
+    setup = time.perf_counter() - t0
+    print(f"solvers created in {setup - t_ops:.1f} s", file=sys.stderr, flush=True)
+    streams = [torch.cuda.Stream() for _ in range(args.streams)]
+    for i in range(args.warmup):
+        step_batched(solvers, streams)
+        print(f"warmup batched step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step_batched(solvers, streams)
+        print(f"timed batched step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cpu = None
+    if not args.no_cpu_baseline:
+        import numpy as np
+        from oracle import sweep
+        steps, tc = 0, time.perf_counter()
+        for w in wls:
+            prob = sweep.Problem.from_workload(w)
+            psi = sweep.dense_psi0(w)
+            nxt, k = prob.power_step(psi, 1.0)
+            steps += 1
+            if time.perf_counter() - tc > args.cpu_seconds:
+                break
+        el = time.perf_counter() - tc
+        cpu = dict(value=steps / el, unit="instance-steps/s",
+                   cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                   kind="oracle", sample=f"first step of {steps} instances in order, {el:.1f} s")
+    out = {
+        "metric": "power-iteration steps/sec & time-to-k at 1e-5, mixed vs FP64; TT GFLOP/s % peak",
+        "value": len(solvers) * args.steps / dt,
+        "unit": "instance-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded)",
+        "config": {"workload": "batch256_uneven", "description": WORKLOADS["batch256_uneven"][1],
+                   "instances": len(solvers), "streams": args.streams,
+                   "setup_seconds": setup},
+        "max_rank": int(max(max(s.native.ranks()) for s in solvers)),
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for s in solvers:
+        s.close()
+    print("solvers closed", file=sys.stderr, flush=True)
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the batch and "
               "single-instance paths are single-device by design.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch256_uneven":
+        return _bench_batch(args)
     import numpy as np
     import torch
     from paper_2309_03347_amd import workload as W

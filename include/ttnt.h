@@ -223,6 +223,21 @@ typedef struct tt_solver_s tt_solver;
 tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
                            tt_solver** out);
 tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);
+/*
+ * tt_power_step_batched - one power step of each of `count` independent
+ * solvers (for example a parameter study of many small problems; each
+ * instance is the iteration of eq. TT_k_eff_fixed_points on its own data).
+ * The steps run concurrently: min(nstreams, count) host threads take the
+ * solvers from a shared list, largest estimated cost first, and thread t
+ * issues its work on streams[t].  Persistent local solves of a thread use at
+ * most (compute units / threads) workgroups, so that the concurrent ones can
+ * all be resident.  infos[i] receives solver i's step information.  Every
+ * solver must appear once.  Returns TT_OK, TT_E_NOCONV if some step hit its
+ * sweep limit, or the first other error of any instance (the remaining
+ * instances still run).  Each stream is synchronized before return.
+ */
+tt_status tt_power_step_batched(tt_solver** solvers, int32_t count, tt_step_info* infos,
+                                const tt_stream* streams, int32_t nstreams);
 /* Copy the current psi into the caller's TT vector (capacity checked); writes out->r. */
 tt_status tt_solver_get_psi(tt_solver* s, tt_vec* out, tt_stream stream);
 /* Current ranks of psi (host array of d+1) and d. */

@@ -1,9 +1,13 @@
 // extern "C" entry points of libttnt.so (declared in include/ttnt.h).
+#include <algorithm>
+#include <optional>
+#include <thread>
 #include <cmath>
 #include <exception>
 #include <string>
 
 #include "engine.h"
+#include "krylov.h"
 #include "kernels.h"
 #include "solver.h"
 #include "ttk.h"
@@ -255,6 +259,113 @@ tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream) {
   });
   if (st == TT_OK && info && info->status == TT_E_NOCONV) return TT_E_NOCONV;
   return st;
+}
+
+tt_status tt_power_step_batched(tt_solver** solvers, int32_t count, tt_step_info* infos,
+                                const tt_stream* streams, int32_t nstreams) {
+  std::vector<tt_status> st;
+  std::vector<std::string> msg;
+  tt_status top = guard([&] {
+    TT_REQUIRE(count >= 0, "count must be >= 0");
+    if (count == 0) return;
+    TT_REQUIRE(solvers && infos && streams, "NULL argument");
+    TT_REQUIRE(nstreams >= 1, "nstreams must be >= 1");
+    std::vector<const tt_solver*> seen(solvers, solvers + count);
+    for (const tt_solver* p : seen) TT_REQUIRE(p != nullptr, "NULL solver in the batch");
+    std::sort(seen.begin(), seen.end());
+    TT_REQUIRE(std::adjacent_find(seen.begin(), seen.end()) == seen.end(),
+               "a solver appears twice in the batch");
+    int dev = 0, cus = 0;
+    TT_HIP(hipGetDevice(&dev));
+    TT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int lanes = std::min<int>(nstreams, count);
+    // largest estimated step cost first
+    std::vector<double> cost(count);
+    for (int i = 0; i < count; ++i) cost[i] = solvers[i]->impl.step_cost();
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    st.assign(count, TT_OK);
+    msg.assign(count, std::string());
+
+    // One host thread keeps up to `lanes` steps in flight, one per stream,
+    // and resumes whichever step's device synchronization has completed.
+    struct Lane {
+      int idx = -1;
+      std::optional<Co> task;
+    };
+    std::vector<Lane> lane(lanes);
+    struct CapScope {
+      explicit CapScope(int c) { krylov_set_thread_cap(c); }
+      ~CapScope() { krylov_set_thread_cap(0); }
+    } cap_scope(std::max(1, cus / lanes));
+    auto finish = [&](int l, tt_status code) {
+      const int idx = lane[l].idx;
+      if (code == TT_OK && infos[idx].status == TT_E_NOCONV) code = TT_E_NOCONV;
+      st[idx] = code;
+      if (code != TT_OK && code != TT_E_NOCONV) msg[idx] = g_err;
+      lane[l].task.reset();
+      lane[l].idx = -1;
+    };
+    // resume lane l's task once; returns true while it is still running
+    auto advance = [&](int l) {
+      Solver& sv = solvers[lane[l].idx]->impl;
+      bool done = false;
+      const tt_status code = guard([&] {
+        sv.enter();
+        try {
+          done = resume_task(*lane[l].task, sv.slot);
+        } catch (...) {
+          sv.leave();
+          throw;
+        }
+        sv.leave();
+      });
+      if (code != TT_OK || done) {
+        finish(l, code);
+        return false;
+      }
+      return true;
+    };
+    int next = 0, running = 0;
+    for (;;) {
+      for (int l = 0; l < lanes && next < count; ++l) {
+        if (lane[l].idx >= 0) continue;
+        lane[l].idx = order[next++];
+        Solver& sv = solvers[lane[l].idx]->impl;
+        sv.slot.resume = nullptr;
+        lane[l].task.emplace(sv.step_co((hipStream_t)streams[l], &infos[lane[l].idx]));
+        ++running;
+        if (!advance(l)) --running;
+      }
+      if (running == 0 && next >= count) break;
+      bool progressed = false;
+      for (int l = 0; l < lanes; ++l) {
+        if (lane[l].idx < 0) continue;
+        const hipError_t q = hipEventQuery(solvers[lane[l].idx]->impl.slot.ev);
+        if (q == hipErrorNotReady) continue;
+        progressed = true;
+        if (q != hipSuccess) {
+          g_err = std::string("event query failed: ") + hipGetErrorString(q);
+          finish(l, TT_E_HIP);
+          --running;
+          continue;
+        }
+        if (!advance(l)) --running;
+      }
+      if (!progressed) std::this_thread::yield();
+    }
+  });
+  if (top != TT_OK) return top;
+  tt_status worst = TT_OK;
+  for (size_t i = 0; i < st.size(); ++i) {
+    const tt_status x = st[i];
+    if (x != TT_OK && (worst == TT_OK || worst == TT_E_NOCONV)) {
+      worst = x;
+      if (x != TT_E_NOCONV) g_err = "batch instance " + std::to_string(i) + ": " + msg[i];
+    }
+  }
+  return worst;
 }
 
 tt_status tt_solver_get_psi(tt_solver* s, tt_vec* out, tt_stream stream) {

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "common.h"
+#include "coro.h"
 
 namespace ttnt {
 
@@ -54,7 +55,16 @@ TTm view(const tt_mat* m);
 
 // y = A x (exact), y ranks R_k r_k.
 void matvec(hipStream_t s, const TTm& A, const TTv& x, TTv& y);
-// In-place rounding; returns relative discarded norm if rel_err != nullptr (synchronizes).
+// Pinned host memory for values a task reads back (at least 4 ints, 4 doubles).
+struct HostBuf {
+  int* i;
+  double* d;
+};
+// In-place rounding as a task (suspends once per truncated core); writes the
+// relative discarded norm to *rel_err (host) if rel_err != nullptr.
+Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws,
+               SyncSlot& slot, HostBuf hb);
+// Blocking form of round_tt_co (synchronizes the stream).
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws);
 size_t round_ws_bytes(const TTv& x);
 // <a, b> into a device scalar `out` (no synchronization).
@@ -91,12 +101,21 @@ struct LocalSolveResult {
   int method = 0;
   double rel_res = 0.0;
   bool converged = true;
+  bool deferred = false;   // iterations / convergence are in the caller's defer_info
+  int probe_slot = -1;     // probe bracket of a deferred persistent solve
 };
 // Scratch for a local solve of N unknowns (LU and/or GMRES).
 size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o);
 // Solve (PhiL (x) A (x) PhiR) x = f; x holds the initial guess.  `final_res`
 // requests the final residual (one extra apply and a synchronization).
+// With defer_info (pinned host, 3 doubles) a persistent GMRES solve does not
+// synchronize: [iterations, converged, residual estimate] land there once the
+// stream reaches this point, and the result is marked deferred.
 LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, double* x,
-                             const LocalSolveOpts& o, Bump& ws, bool final_res);
+                             const LocalSolveOpts& o, Bump& ws, bool final_res,
+                             double* defer_info = nullptr);
+// Work of a persistent GMRES solve (for the kernel probe), once its iteration
+// count is known.
+void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot);
 
 }  // namespace ttnt

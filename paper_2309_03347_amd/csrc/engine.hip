@@ -117,7 +117,36 @@ size_t round_ws_bytes(const TTv& x) {
   return b.used + 4096;
 }
 
+namespace {
+// Event and pinned scratch for blocking calls made by one host thread (kept
+// for the life of the process).
+struct BlockingCtx {
+  SyncSlot slot;
+  HostBuf hb{nullptr, nullptr};
+};
+BlockingCtx& blocking_ctx() {
+  thread_local BlockingCtx* c = nullptr;
+  if (!c) {
+    auto* n = new BlockingCtx();
+    TT_HIP(hipEventCreateWithFlags(&n->slot.ev, hipEventDisableTiming));
+    void* p = nullptr;
+    TT_HIP(hipHostMalloc(&p, 256, hipHostMallocDefault));
+    n->hb.i = static_cast<int*>(p);
+    n->hb.d = reinterpret_cast<double*>(static_cast<char*>(p) + 64);
+    c = n;
+  }
+  return *c;
+}
+}  // namespace
+
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws) {
+  BlockingCtx& c = blocking_ctx();
+  Co t = round_tt_co(s, x, tol, rmax, rel_err, ws, c.slot, c.hb);
+  run_blocking(t, c.slot);
+}
+
+Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws,
+               SyncSlot& slot, HostBuf hb) {
   const int d = x.d;
   const int64_t mc = max_core(x);
   const int md = max_dim(x);
@@ -140,7 +169,7 @@ void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump
   double* disc = scal + 1;
   if (d == 1) {
     if (rel_err) *rel_err = 0.0;
-    return;
+    co_return;
   }
   // left-to-right Householder QR sweep
   for (int k = 0; k < d - 1; ++k) {
@@ -162,9 +191,9 @@ void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump
     SvdScratch sc = carve_svd(sub, rows, cols);
     const int p = thin_svd(s, x.core(k), rows, cols, Lft, S, RtT, sc);
     trunc_rank(s, S, p, tol, (double)(d - 1), nrm2, rmax, irank, disc);
-    int rk = 0;
-    TT_HIP(hipMemcpyAsync(&rk, irank, sizeof(int), hipMemcpyDeviceToHost, s));
-    TT_HIP(hipStreamSynchronize(s));
+    TT_HIP(hipMemcpyAsync(hb.i, irank, sizeof(int), hipMemcpyDeviceToHost, s));
+    co_await Sync{&slot, s};
+    const int rk = hb.i[0];
     copy(s, RtT, x.core(k), (int64_t)rk * cols);
     const int prow = x.r[k - 1] * x.n[k - 1];
     gemm(s, false, false, prow, rk, rows, 1.0, x.core(k - 1), rows, 0, Lft, p, 0, 0.0, tmp, rk, 0);
@@ -173,10 +202,9 @@ void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump
     x.r[k] = rk;
   }
   if (rel_err) {
-    double h[2];
-    TT_HIP(hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    TT_HIP(hipStreamSynchronize(s));
-    *rel_err = h[0] > 0.0 ? std::sqrt(h[1] / h[0]) : 0.0;
+    TT_HIP(hipMemcpyAsync(hb.d, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    co_await Sync{&slot, s};
+    *rel_err = hb.d[0] > 0.0 ? std::sqrt(hb.d[1] / hb.d[0]) : 0.0;
   }
 }
 
@@ -283,8 +311,31 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
   return (size_t)need + 1024;
 }
 
+void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot) {
+  if (!g_probe || slot < 0) return;
+  const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
+  const int m = krylov_restart(sh, std::max(2, std::min(restart, 88)));
+  if (m <= 0) return;
+  const int64_t N = (int64_t)op.ra * op.n * op.rc;
+  // one operator application per Arnoldi step and per restart residual, and
+  // the two Gram-Schmidt passes over j + 1 vectors
+  const int64_t T = iterations;
+  const int64_t full = T / m, rem = T % m;
+  const double sumj = (double)full * m * (m + 1) / 2 + (double)rem * (rem + 1) / 2;
+  const int64_t applies = T + std::max<int64_t>(1, (T + m - 1) / m);
+  const double fa = 2.0 * ((double)op.ra * op.RL * op.n * op.rd * op.rb +
+                           (double)op.ra * op.m * op.RR * op.RL * op.n * op.rd +
+                           (double)op.ra * op.m * op.rc * op.RR * op.rd);
+  const double ba = 8.0 * ((double)op.ra * op.RL * op.rb + (double)op.m * op.RR * op.RL * op.n +
+                           (double)op.rc * op.RR * op.rd + 2.0 * N);
+  const double fl = applies * fa + 8.0 * N * sumj + 6.0 * N * T;
+  const double by = applies * ba + 8.0 * N * (2.0 * sumj + 4.0 * T);
+  g_probe->amend(slot, fl, by);
+}
+
 LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, double* x,
-                             const LocalSolveOpts& o, Bump& ws, bool final_res) {
+                             const LocalSolveOpts& o, Bump& ws, bool final_res,
+                             double* defer_info) {
   LocalSolveResult res;
   const int64_t N = (int64_t)op.ra * op.n * op.rc;
   TT_REQUIRE(op.ra == op.rb && op.rc == op.rd && op.m == op.n, "local system must be square");
@@ -329,27 +380,18 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     double* kws = ws.d(kw);
     const bool probed = krylov_solve(s, sh, op.phiL, op.Ap, op.phiR, f, x, m, o.max_iter, o.tol,
                                      o.eta, kws, kw, scal, grid);
-    double info[3];
-    TT_HIP(hipMemcpyAsync(info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
-    TT_HIP(hipStreamSynchronize(s));
-    res.iterations = (int)info[0];
-    res.converged = info[1] != 0.0;
-    if (probed) {
-      // algorithmic work: one operator application per Arnoldi step and per
-      // restart residual, and the two Gram-Schmidt passes over j + 1 vectors
-      const int m = krylov_restart(sh, std::max(2, std::min(o.restart, 88)));
-      const int64_t T = res.iterations;
-      const int64_t full = T / m, rem = T % m;
-      const double sumj = (double)full * m * (m + 1) / 2 + (double)rem * (rem + 1) / 2;
-      const int64_t applies = T + std::max<int64_t>(1, (T + m - 1) / m);
-      const double fa = 2.0 * ((double)op.ra * op.RL * op.n * op.rd * op.rb +
-                               (double)op.ra * op.m * op.RR * op.RL * op.n * op.rd +
-                               (double)op.ra * op.m * op.rc * op.RR * op.rd);
-      const double ba = 8.0 * ((double)op.ra * op.RL * op.rb + (double)op.m * op.RR * op.RL * op.n +
-                               (double)op.rc * op.RR * op.rd + 2.0 * N);
-      const double fl = applies * fa + 8.0 * N * sumj + 6.0 * N * T;
-      const double by = applies * ba + 8.0 * N * (2.0 * sumj + 4.0 * T);
-      g_probe->amend_last(fl, by);
+    const int slot = probed ? g_probe->last_slot() : -1;
+    if (defer_info && !final_res) {
+      TT_HIP(hipMemcpyAsync(defer_info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      res.deferred = true;
+      res.probe_slot = slot;
+    } else {
+      double info[3];
+      TT_HIP(hipMemcpyAsync(info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      TT_HIP(hipStreamSynchronize(s));
+      res.iterations = (int)info[0];
+      res.converged = info[1] != 0.0;
+      krylov_probe_amend(op, o.restart, res.iterations, slot);
     }
   } else {
     res.method = method;

@@ -18,6 +18,11 @@ constexpr int kKrylovMaxGrid = 64;
 
 // Grid cap in use (kKrylovMaxGrid unless overridden).
 int krylov_grid();
+// Caps the grid of persistent solves issued by the calling host thread (0
+// restores the default).  Concurrent solves on several streams keep the sum
+// of their grids within the compute-unit count, so that all of them can be
+// resident at once.
+void krylov_set_thread_cap(int cap);
 // Restart length the persistent solver uses for `restart` (smaller when the
 // LDS-resident basis would not fit), 0 when the shape is not supported.
 int krylov_restart(const KrylovShape& sh, int restart);

@@ -22,6 +22,7 @@
 // the iteration count is bounded by max_iter.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "gemm_tile.h"
 #include "krylov.h"
@@ -511,25 +512,38 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
 }
 
 struct DevInfo {
-  int device = -1;
   int cus = 0;
   int lds_max = 0;
 };
 
-const DevInfo& dev_info() {
-  thread_local DevInfo di;
+constexpr int kMaxDev = 64;
+std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
+
+// Device properties, and the kernel's LDS attribute raised once per device
+// and process.
+DevInfo dev_info() {
+  static DevInfo di[kMaxDev];
+  static bool ready[kMaxDev] = {};
   int dev = 0;
   TT_HIP(hipGetDevice(&dev));
-  if (di.device != dev) {
-    TT_HIP(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  TT_REQUIRE(dev >= 0 && dev < kMaxDev, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  if (!ready[dev]) {
+    DevInfo d;
+    TT_HIP(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
     int coop = 0;
     TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     TT_REQUIRE(coop != 0, "device does not support cooperative launches");
-    TT_HIP(hipDeviceGetAttribute(&di.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    di.device = dev;
+    TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(gmres_slices_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
+    di[dev] = d;
+    ready[dev] = true;
   }
-  return di;
+  return di[dev];
 }
+
+thread_local int t_cap_override = 0;
 
 int grid_cap() {
   static const int want = [] {
@@ -537,7 +551,7 @@ int grid_cap() {
     const int v = e ? std::atoi(e) : 0;
     return v > 0 ? v : kKrylovMaxGrid;
   }();
-  return want;
+  return t_cap_override > 0 ? std::min(want, t_cap_override) : want;
 }
 
 struct Plan {
@@ -583,6 +597,8 @@ bool krylov_enabled() {
 
 int krylov_grid() { return grid_cap(); }
 
+void krylov_set_thread_cap(int cap) { t_cap_override = cap > 0 ? cap : 0; }
+
 bool krylov_fits(const KrylovShape& sh, int restart) {
   if (restart < 2 || sh.r0 <= 0 || sh.r1 <= 0 || sh.n <= 0 || sh.RL <= 0 || sh.RR <= 0)
     return false;
@@ -609,7 +625,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
                   double tol, double eta, double* ws, size_t ws_doubles, double* info,
                   int /*grid*/) {
   TT_REQUIRE(max_iter >= 0, "Krylov solve: negative iteration limit");
-  const DevInfo& di = dev_info();
+  const DevInfo di = dev_info();
   const Plan p = make_plan(sh, restart, di.lds_max);
   TT_REQUIRE(p.G > 0, "Krylov solve: local system too large for the LDS-resident basis");
   TT_REQUIRE(ws_doubles >= krylov_ws_doubles(sh, restart, 0), "Krylov solve: workspace too small");
@@ -648,12 +664,6 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.info = info;
   TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
 
-  static thread_local int attr_bytes = -1;
-  if (attr_bytes < (int)p.lds_bytes) {
-    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(gmres_slices_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, di.lds_max - 1024));
-    attr_bytes = di.lds_max - 1024;
-  }
   int per_cu = 0;
   TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, reinterpret_cast<const void*>(gmres_slices_kernel), kThreads, p.lds_bytes));
@@ -664,8 +674,11 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   hipEvent_t pe = nullptr;
   if (g_probe) pe = g_probe->begin(s, kProbeKrylov, 0.0, 0.0);   // work amended after the run
   void* args[] = {&a};
-  TT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gmres_slices_kernel),
-                                    dim3(p.G), dim3(kThreads), args, p.lds_bytes, s));
+  {
+    std::lock_guard<std::mutex> lock(g_dev_mu);
+    TT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gmres_slices_kernel),
+                                      dim3(p.G), dim3(kThreads), args, p.lds_bytes, s));
+  }
   if (pe) g_probe->end(s);
   return pe != nullptr;
 }

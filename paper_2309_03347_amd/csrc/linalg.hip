@@ -3,6 +3,7 @@
 // (the matrices are small and stay in cache).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -692,21 +693,27 @@ size_t svd_lds_doubles(int m, int n) {
          4 * ((size_t)n + 1) + 8;
 }
 
-// Largest dynamic LDS allocation of one workgroup on the current device (bytes).
+// Largest dynamic LDS allocation of one workgroup on the current device
+// (bytes).  The kernels' attributes are raised once per device and process.
 int lds_limit() {
-  thread_local int dev = -1, lim = 0;
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static int lim[kMaxDev] = {};
   int d = 0;
   TT_HIP(hipGetDevice(&d));
-  if (d != dev) {
-    TT_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, d));
-    lim -= 1024;
+  TT_REQUIRE(d >= 0 && d < kMaxDev, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (lim[d] == 0) {
+    int v = 0;
+    TT_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d));
+    v -= 1024;
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(qr_lds_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_lds_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim));
-    dev = d;
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    lim[d] = v;
   }
-  return lim;
+  return lim[d];
 }
 
 }  // namespace

@@ -27,9 +27,11 @@ struct Probe {
   // Returns the start event to record before a launch of class c, or nullptr.
   hipEvent_t begin(hipStream_t s, int c, double flops, double bytes);
   void end(hipStream_t s);
-  // Replaces the work recorded for the most recent bracket (for launches whose
-  // work is known only after they ran).
+  // Replaces the work recorded for the most recent bracket, or for bracket
+  // `slot` (for launches whose work is known only after they ran).
   void amend_last(double flops, double bytes);
+  int last_slot() const { return (int)used - 1; }
+  void amend(int slot, double flops, double bytes);
   // Waits for the window's events and folds them into the totals.
   void close();
   void reset();

@@ -57,6 +57,12 @@ void Probe::amend_last(double f, double b) {
   bytes[used - 1] = b;
 }
 
+void Probe::amend(int slot, double f, double b) {
+  if (slot < 0 || (size_t)slot >= used) return;
+  flops[slot] = f;
+  bytes[slot] = b;
+}
+
 void Probe::calibrate(hipStream_t s) {
   // empty brackets queued behind a hold: the event pair's own interval
   if (ev.empty()) begin(s, 0, 0.0, 0.0), end(s), used = 0;

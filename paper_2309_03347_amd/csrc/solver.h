@@ -1,6 +1,7 @@
 // Power-iteration solver state (one instance per tt_solver handle).
 #pragma once
 
+#include "coro.h"
 #include "engine.h"
 #include "probe.h"
 
@@ -53,14 +54,35 @@ struct Solver {
   double *scal = nullptr, *resarr = nullptr;
   int* irank = nullptr;
 
+  // host synchronization of the step task: its event and pinned readbacks
+  SyncSlot slot;
+  void* hostmem = nullptr;
+  double* h_res = nullptr;    // d local residuals
+  double* h_k = nullptr;      // k, k_prev
+  double* h_kry = nullptr;    // 3 per core: persistent GMRES [iterations, converged, res]
+  HostBuf hb{nullptr, nullptr};
+  std::vector<char> kry_pending;
+  std::vector<int> kry_slot;
+  std::vector<LocalOp> kry_op;
+  int64_t launch_acc = 0;
+
   ~Solver();
   void create(const tt_problem* p, const tt_solver_opts* o);
+  // One power step, blocking.
   void step(hipStream_t s, tt_step_info* info);
+  // One power step as a task; drive it between enter() and leave().
+  Co step_co(hipStream_t s, tt_step_info* info);
+  // Bind / release this solver's thread-local context (split-K scratch,
+  // kernel probe, launch counter) around each resumption of its task.
+  void enter();
+  void leave();
+  // Rough relative cost of one step at the current ranks (orders batches).
+  double step_cost() const;
 
  private:
   void plan(Bump& b);
-  void sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
-                  const std::vector<double*>& ApOp, StepStats& st);
+  Co sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
+                   const std::vector<double*>& ApOp, StepStats& st);
 };
 
 

@@ -210,6 +210,22 @@ void Solver::plan(Bump& b) {
 
 Solver::~Solver() {
   if (mem) (void)hipFree(mem);
+  if (slot.ev) (void)hipEventDestroy(slot.ev);
+  if (hostmem) (void)hipHostFree(hostmem);
+}
+
+void Solver::enter() {
+  g_splitk_buf = splitk;
+  g_splitk_cap = kSplitK;
+  g_probe = probe.active ? &probe : nullptr;
+  g_launches = launch_acc;
+}
+
+void Solver::leave() {
+  launch_acc = g_launches;
+  g_splitk_buf = nullptr;
+  g_splitk_cap = 0;
+  g_probe = nullptr;
 }
 
 void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
@@ -293,6 +309,16 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   plan(dry);
   mem_bytes = dry.used + 4096;
   TT_HIP(hipMalloc(&mem, mem_bytes));
+  TT_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
+  TT_HIP(hipHostMalloc(&hostmem, (size_t)(4 * d + 32) * sizeof(double), hipHostMallocDefault));
+  h_res = static_cast<double*>(hostmem);
+  h_k = h_res + d;
+  h_kry = h_k + 2;
+  hb.d = h_kry + 3 * d;
+  hb.i = reinterpret_cast<int*>(hb.d + 8);
+  kry_pending.assign(d, 0);
+  kry_slot.assign(d, -1);
+  kry_op.assign(d, LocalOp{});
   Bump real;
   real.base = (char*)mem;
   real.cap = mem_bytes;
@@ -369,8 +395,8 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   TT_HIP(hipDeviceSynchronize());
 }
 
-void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
-                        const std::vector<double*>& ApOp, StepStats& st) {
+Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
+                         const std::vector<double*>& ApOp, StepStats& st) {
   const int rk = X.r[k], rk1 = X.r[k + 1], nk = n[k];
   const int vk = V.r[k], vk1 = V.r[k + 1];
   LocalOp xh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RXH[k + 1], rk1, rk1,
@@ -388,11 +414,18 @@ void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   // solves only need to reduce their residual by a fixed factor.
   LocalSolveOpts lo = lso;
   if (cap_bound) lo.eta = cap_eta;
-  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lo, lw, false);
-  st.local_iters += lr.iterations;
+  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lo, lw, false, h_kry + 3 * k);
+  if (lr.deferred) {
+    // iterations are read at the end of the sweep
+    kry_pending[k] = 1;
+    kry_slot[k] = lr.probe_slot;
+    kry_op[k] = xh;
+  } else {
+    st.local_iters += lr.iterations;
+  }
   if (k == d - 1) {
     copy(s, xloc, X.core(k), N);
-    return;
+    co_return;
   }
   // truncated SVD of the solved core, (r_k n_k) x r_{k+1}
   const int rows = rk * nk, cols = rk1;
@@ -416,11 +449,10 @@ void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
     transpose(s, sU, cols, rows, rows, RtT, cols);
   }
   trunc_rank(s, Sv, p, tol, (double)d, nullptr, rmax, irank, nullptr);
-  int rr[2] = {0, 0};
-  TT_HIP(hipMemcpyAsync(rr, irank, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-  TT_HIP(hipStreamSynchronize(s));
-  const int rt = rr[0];
-  if (rr[1]) st.cap_hit = true;
+  TT_HIP(hipMemcpyAsync(hb.i, irank, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  co_await Sync{&slot, s};
+  const int rt = hb.i[0];
+  if (hb.i[1]) st.cap_hit = true;
   const int kz = Z.r[k + 1];
   const int w = rt + kz;
   // U2 = [u | crz]
@@ -462,16 +494,31 @@ void Solver::sweep_core(hipStream_t s, int k, const TTv& V, const TTm& Aop,
              vk1, LZA[k + 1], T1, T2);
 }
 
+double Solver::step_cost() const {
+  // local operator applications dominate: n r^3 R + n^2 r^2 R^2 per core
+  double c = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double r = std::max(psi.r[k], psi.r[k + 1]), R = std::max(RH[k], RH[k + 1]);
+    c += n[k] * r * r * r * R + (double)n[k] * n[k] * r * r * R * R;
+  }
+  return c;
+}
+
 void Solver::step(hipStream_t s, tt_step_info* info) {
+  enter();
+  try {
+    Co t = step_co(s, info);
+    run_blocking(t, slot);
+  } catch (...) {
+    leave();
+    throw;
+  }
+  leave();
+}
+
+Co Solver::step_co(hipStream_t s, tt_step_info* info) {
   g_launches = 0;
-  struct SplitScope {
-    SplitScope(double* p, size_t c) { g_splitk_buf = p; g_splitk_cap = c; }
-    ~SplitScope() { g_splitk_buf = nullptr; g_splitk_cap = 0; }
-  } split_scope(splitk, kSplitK);
-  struct ProbeScope {
-    explicit ProbeScope(Probe* p) { g_probe = p; }
-    ~ProbeScope() { g_probe = nullptr; }
-  } probe_scope(probe.active ? &probe : nullptr);
+  std::fill(kry_pending.begin(), kry_pending.end(), 0);
   if (probe.active && probe.overhead_ms == 0.0) probe.calibrate(s);
   StepStats st;
   // A(k) core 0 = SF_0 + F_0 / k
@@ -487,7 +534,7 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
   if (rhs_mode == 1) {
     matvec(s, Ak, psi, B);
     w.used = 0;
-    round_tt(s, B, tol, rhs_rmax, nullptr, w);
+    co_await round_tt_co(s, B, tol, rhs_rmax, nullptr, w, slot, hb);
     V = &B;
     Aop = &Id;
     ApOp = &ApI;
@@ -513,12 +560,18 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
       iface_right(s, RZA[k + 1], Z.core(k), Z.r[k], Z.r[k + 1], (*ApOp)[k], Rop[k], n[k], n[k],
                   Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RZA[k], T1, T2);
     }
-    for (int k = 0; k < d; ++k) sweep_core(s, k, *V, *Aop, *ApOp, st);
-    std::vector<double> res(d);
-    TT_HIP(hipMemcpyAsync(res.data(), resarr, d * sizeof(double), hipMemcpyDeviceToHost, s));
-    TT_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < d; ++k) co_await sweep_core_co(s, k, *V, *Aop, *ApOp, st);
+    TT_HIP(hipMemcpyAsync(h_res, resarr, d * sizeof(double), hipMemcpyDeviceToHost, s));
+    co_await Sync{&slot, s};
     max_res = 0.0;
-    for (double v : res) max_res = std::max(max_res, v);
+    for (int k = 0; k < d; ++k) max_res = std::max(max_res, h_res[k]);
+    for (int k = 0; k < d; ++k) {
+      if (!kry_pending[k]) continue;
+      const int it = (int)h_kry[3 * k];
+      st.local_iters += it;
+      krylov_probe_amend(kry_op[k], lso.restart, it, kry_slot[k]);
+      kry_pending[k] = 0;
+    }
     ++sweeps;
     if (!(max_res == max_res)) throw NumericError{};
     if (max_res < tol) break;
@@ -530,7 +583,7 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
   // compress the solution and update k
   double trunc = 0.0;
   w.used = 0;
-  round_tt(s, X, tol, rmax, &trunc, w);
+  co_await round_tt_co(s, X, tol, rmax, &trunc, w, slot, hb);
   w.used = 0;
   dot_tt(s, cF, X, scal + NUM, w);
   k_update(s, scal + KVAL, scal + NUM, scal + DEN, scal + KINFO);
@@ -539,9 +592,9 @@ void Solver::step(hipStream_t s, tt_step_info* info) {
   scale_ratio(s, scal + NUM, scal + NRM2, scal + DEN);
   psi.r = X.r;
   for (int k = 0; k < d; ++k) copy(s, X.core(k), psi.core(k), X.size(k));
-  double kinfo[2];
-  TT_HIP(hipMemcpyAsync(kinfo, scal + KINFO, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  TT_HIP(hipStreamSynchronize(s));
+  TT_HIP(hipMemcpyAsync(h_k, scal + KINFO, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  co_await Sync{&slot, s};
+  const double kinfo[2] = {h_k[0], h_k[1]};
   k_host = kinfo[0];
   if (probe.active) probe.close();
   if (info) {

@@ -24,7 +24,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_dot_workspace", "tt_dot", "tt_local_solve_workspace", "tt_local_solve",
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
-            "tt_solver_probe_stats"]
+            "tt_solver_probe_stats", "tt_power_step_batched"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -130,6 +130,9 @@ def lib():
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
+        L.tt_power_step_batched.argtypes = [ctypes.POINTER(v), ctypes.c_int32,
+                                            ctypes.POINTER(TTStepInfo), ctypes.POINTER(v),
+                                            ctypes.c_int32]
         L.tt_solver_get_psi.argtypes = [v, ctypes.POINTER(TTVec), v]
         L.tt_solver_ranks.argtypes = [v, I32P, I32P]
         L.tt_solver_launches.argtypes = [v]
@@ -299,6 +302,29 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
                    converged=st == TT_OK)
 
 
+def _info_dict(info) -> dict:
+    return dict(k=info.k, k_prev=info.k_prev, dk=info.dk, max_local_res=info.max_local_res,
+                trunc_err=info.trunc_err, sweeps=info.sweeps, max_rank=info.max_rank,
+                local_iters=info.local_iters, status=info.status)
+
+
+def power_step_batched(solvers, streams) -> list:
+    """One power step of every solver, concurrently on the given torch streams
+    (tt_power_step_batched).  Returns the step infos in the solvers' order."""
+    torch = _torch()
+    n = len(solvers)
+    if n == 0:
+        return []
+    handles = (ctypes.c_void_p * n)(*[s.h.value for s in solvers])
+    infos = (TTStepInfo * n)()
+    sarr = (ctypes.c_void_p * len(streams))(*[st.cuda_stream for st in streams])
+    # the solvers' earlier work was issued on the current stream
+    torch.cuda.current_stream().synchronize()
+    st = lib().tt_power_step_batched(handles, n, infos, sarr, len(streams))
+    _check(st, allow=(TT_E_NOCONV,))
+    return [_info_dict(infos[i]) for i in range(n)]
+
+
 class Solver:
     """Handle of a device power-iteration solver (tt_solver_create ... destroy)."""
 
@@ -323,9 +349,7 @@ class Solver:
         info = TTStepInfo()
         st = lib().tt_power_step(self.h, ctypes.byref(info), _stream())
         _check(st, allow=(TT_E_NOCONV,))
-        return dict(k=info.k, k_prev=info.k_prev, dk=info.dk, max_local_res=info.max_local_res,
-                    trunc_err=info.trunc_err, sweeps=info.sweeps, max_rank=info.max_rank,
-                    local_iters=info.local_iters, status=info.status)
+        return _info_dict(info)
 
     def ranks(self) -> np.ndarray:
         r = np.zeros(self.d + 1, dtype=np.int32)

@@ -115,3 +115,18 @@ class KeffSolver:
 
     def close(self):
         self.native.close()
+
+
+def step_batched(solvers: List["KeffSolver"], streams) -> List[StepRecord]:
+    """One power step of each KeffSolver, run concurrently on `streams`
+    (torch.cuda.Stream objects; one host thread per stream in the library)."""
+    t0 = time.perf_counter()
+    infos = native.power_step_batched([s.native for s in solvers], streams)
+    dt = time.perf_counter() - t0
+    recs = []
+    for s, info in zip(solvers, infos):
+        rec = StepRecord(info["k"], info["dk"], info["sweeps"], info["max_rank"],
+                         info["max_local_res"], info["trunc_err"], info["local_iters"], dt)
+        s.history.append(rec)
+        recs.append(rec)
+    return recs

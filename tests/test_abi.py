@@ -109,3 +109,18 @@ def test_solver_rejects_bad_options():
     prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, -1.0)  # k0 <= 0
     opts = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64)
     assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
+
+
+def test_batched_step_validates_arguments():
+    lib = native.lib()
+    infos = (native.TTStepInfo * 2)()
+    streams = (ctypes.c_void_p * 1)(None)
+    assert lib.tt_power_step_batched(None, 0, None, None, 0) == native.TT_OK   # empty batch
+    assert lib.tt_power_step_batched(None, -1, infos, streams, 1) == native.TT_E_ARG
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.tt_power_step_batched(nulls, 2, infos, streams, 0) == native.TT_E_ARG
+    assert lib.tt_power_step_batched(nulls, 2, infos, streams, 1) == native.TT_E_ARG
+    assert b"NULL solver" in lib.tt_last_error()
+    twice = (ctypes.c_void_p * 2)(0x1000, 0x1000)     # never dereferenced: rejected first
+    assert lib.tt_power_step_batched(twice, 2, infos, streams, 1) == native.TT_E_ARG
+    assert b"twice" in lib.tt_last_error()
