@@ -28,6 +28,28 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
+# HBM bytes per launch of a kernel class from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters scaled by a plain copy (profiles/gmres_slices_inner_box_n32_G4_S4_traffic.md),
+# valid only while the kernel's sources are unchanged.
+MEASURED_TRAFFIC = {
+    ("krylov", "inner_box_n32_G4_S4"): dict(
+        bytes_per_launch=19.19e6,
+        sources={"paper_2309_03347_amd/csrc/krylov.hip": "885ba82cda4d33b4",
+                 "paper_2309_03347_amd/csrc/gemm_tile.h": "a9a928d54389a255"}),
+}
+
+
+def _measured_traffic(kernel, workload):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None:
+        return None
+    for path, prefix in rec["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != prefix:
+                return None
+    return rec["bytes_per_launch"]
+
 WORKLOADS = {
     # name: (builder, description)
     "inner_box_n32_G4_S4": (lambda W: W.config(1),
@@ -240,6 +262,7 @@ def main():
             achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
             roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                             frac=achieved / PEAK_HBM_GBS, traffic=None)
+        roofline["traffic"] = _measured_traffic(name, args.workload)
         roofline.update(kernel=name, intensity_flop_per_byte=intensity,
                         launches=st["launches"], avg_us=avg_ms * 1e3,
                         flops_per_launch=st["flops"] / max(1, st["launches"]),
