@@ -76,6 +76,8 @@ def _parse():
     p.add_argument("--build-workers", type=int, default=1,
                    help="host processes building the batched workload's operators")
     p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
+    p.add_argument("--no-mixed", action="store_true",
+                   help="skip the mixed-precision comparison run")
     p.add_argument("--ttk-steps", type=int, default=60,
                    help="step limit of the time-to-k run (0 skips it)")
     return p.parse_args()
@@ -272,6 +274,28 @@ def main():
     if args.ttk_steps > 0:
         ttk = _time_to_k(wl, rmax, args.rhs_mode, args.ttk_steps)
 
+    mixed = None
+    if not args.no_mixed:
+        # the same workload with FP32 Arnoldi cycles refining FP64 local residuals
+        sm = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode, ops=s.ops, precision=1)
+        for _ in range(args.warmup):
+            sm.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sm.step()
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        hm = sm.history
+        mixed = dict(value=args.steps / dtm, unit="steps/s", ms_per_step=1e3 * dtm / args.steps,
+                     speedup_vs_fp64=(args.steps / dtm) / value, k=hm[-1].k,
+                     # the FP64 solver's k after the same number of steps
+                     k_rel_diff_vs_fp64=abs(hm[-1].k - hist[len(hm) - 1].k) / abs(hist[len(hm) - 1].k),
+                     local_iters_last=hm[-1].local_iters,
+                     fp64_local_iters_last=hist[len(hm) - 1].local_iters,
+                     dtype="f32 Krylov cycles, f64 residuals / QR / SVD / k")
+        sm.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(wl, args.cpu_seconds)
@@ -299,6 +323,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_k": ttk,
+        "mixed": mixed,
     }
     if probe is not None:
         out["kernel_probe"] = {k: dict(launches=v["launches"], ms=round(v["total_ms"], 3))

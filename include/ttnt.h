@@ -147,6 +147,8 @@ typedef struct {
   int32_t max_iter;     /* total GMRES iterations */
   int32_t restart;      /* Krylov dimension per cycle */
   int32_t direct_max;   /* auto: LU up to this many unknowns */
+  int32_t precision;    /* GMRES (method 2): 0 FP64; 1 mixed - FP32 Arnoldi cycles as
+                           iterative refinement of the FP64 residual, converged in FP64 */
 } tt_solve_opts;
 
 typedef struct {
@@ -204,6 +206,8 @@ typedef struct {
   int32_t gmres_restart;
   int32_t gmres_max_iter;
   int32_t direct_max;    /* local systems up to this size use dense LU */
+  int32_t precision;     /* local GMRES: 0 FP64, 1 mixed (FP32 Arnoldi, FP64 refinement);
+                            everything else in the step stays FP64 */
 } tt_solver_opts;
 
 typedef struct {

@@ -96,6 +96,8 @@ LocalSolveOpts solve_opts_from(const tt_solve_opts* o) {
     so.max_iter = o->max_iter > 0 ? o->max_iter : 1000;
     so.restart = o->restart > 0 ? o->restart : 80;
     so.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
+    TT_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 or 1");
+    so.mixed = o->precision == 1;
   }
   return so;
 }

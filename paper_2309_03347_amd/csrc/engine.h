@@ -95,6 +95,8 @@ struct LocalSolveOpts {
   int restart = 60;
   int direct_max = 256;    // auto: dense LU up to this many unknowns
   int block_max = 1024;    // auto: mode-diagonal cores solved as n blocks up to this size
+  bool mixed = false;      // persistent GMRES: FP32 Arnoldi, FP64 residual refinement
+  double inner_tol = 1e-5; // mixed: an FP32 cycle ends once its residual fell by this factor
 };
 struct LocalSolveResult {
   int iterations = 0;
@@ -103,6 +105,7 @@ struct LocalSolveResult {
   bool converged = true;
   bool deferred = false;   // iterations / convergence are in the caller's defer_info
   int probe_slot = -1;     // probe bracket of a deferred persistent solve
+  bool mixed = false;      // the persistent solve ran FP32 Arnoldi cycles
 };
 // Scratch for a local solve of N unknowns (LU and/or GMRES).
 size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o);
@@ -116,6 +119,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
                              double* defer_info = nullptr);
 // Work of a persistent GMRES solve (for the kernel probe), once its iteration
 // count is known.
-void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot);
+void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot,
+                        bool mixed = false);
 
 }  // namespace ttnt

@@ -311,10 +311,10 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
   return (size_t)need + 1024;
 }
 
-void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot) {
+void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot, bool mixed) {
   if (!g_probe || slot < 0) return;
   const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
-  const int m = krylov_restart(sh, std::max(2, std::min(restart, 88)));
+  const int m = krylov_restart(sh, std::max(2, std::min(restart, 88)), mixed);
   if (m <= 0) return;
   const int64_t N = (int64_t)op.ra * op.n * op.rc;
   // one operator application per Arnoldi step and per restart residual, and
@@ -375,11 +375,13 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     res.method = 2;
     const int m = std::max(2, std::min(o.restart, 88));
     const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
+    const bool mixed = o.mixed && krylov_fits(sh, m, true);
+    res.mixed = mixed;
     const int grid = krylov_grid();
     const size_t kw = krylov_ws_doubles(sh, m, grid);
     double* kws = ws.d(kw);
     const bool probed = krylov_solve(s, sh, op.phiL, op.Ap, op.phiR, f, x, m, o.max_iter, o.tol,
-                                     o.eta, kws, kw, scal, grid);
+                                     o.eta, kws, kw, scal, grid, mixed, o.inner_tol);
     const int slot = probed ? g_probe->last_slot() : -1;
     if (defer_info && !final_res) {
       TT_HIP(hipMemcpyAsync(defer_info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -391,7 +393,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
       TT_HIP(hipStreamSynchronize(s));
       res.iterations = (int)info[0];
       res.converged = info[1] != 0.0;
-      krylov_probe_amend(op, o.restart, res.iterations, slot);
+      krylov_probe_amend(op, o.restart, res.iterations, slot, mixed);
     }
   } else {
     res.method = method;

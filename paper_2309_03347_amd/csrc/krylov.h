@@ -25,21 +25,26 @@ int krylov_grid();
 void krylov_set_thread_cap(int cap);
 // Restart length the persistent solver uses for `restart` (smaller when the
 // LDS-resident basis would not fit), 0 when the shape is not supported.
-int krylov_restart(const KrylovShape& sh, int restart);
+int krylov_restart(const KrylovShape& sh, int restart, bool mixed = false);
 // Whether local GMRES solves use the persistent kernel (default on; the
 // environment variable TTNT_KRYLOV=0 selects the multi-launch path).
 bool krylov_enabled();
 // True when the persistent solver handles this shape on the current device
 // (queries the device).
-bool krylov_fits(const KrylovShape& sh, int restart);
+bool krylov_fits(const KrylovShape& sh, int restart, bool mixed = false);
 size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int grid);
 // GMRES(restart) from the initial guess in x; stops when ||r|| <= max(tol ||f||,
 // eta ||r_0||) or after max_iter Arnoldi steps.  info (device, 3 doubles)
 // receives [iterations, converged (0/1), final residual estimate / ||f||].
-// One cooperative launch (plus a one-element fill of the barrier counter).
-// Returns true when the launch was bracketed by the kernel probe.
+// mixed: the Arnoldi iterations run in FP32 and each restart cycle is one
+// step of iterative refinement on the FP64 residual (a cycle ends once its
+// own residual fell by inner_tol); convergence is judged on the FP64 residual.
+// One cooperative launch (plus a one-element fill of the barrier counter and,
+// when mixed, an FP32 copy of PhiR).  Returns true when the launch was
+// bracketed by the kernel probe.
 bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, const double* Ap,
                   const double* phiR, const double* f, double* x, int restart, int max_iter,
-                  double tol, double eta, double* ws, size_t ws_doubles, double* info, int grid);
+                  double tol, double eta, double* ws, size_t ws_doubles, double* info, int grid,
+                  bool mixed = false, double inner_tol = 1e-5);
 
 }  // namespace ttnt

@@ -45,17 +45,20 @@ struct SArgs {
   const double* phiL;   // [r0][RL][r0]
   const double* Ap;     // [(i, RR), (RL, j)]
   const double* phiR;   // [r1][RR][r1]
+  const void* phiRw;    // phiR in the working precision (phiR itself in FP64 mode)
   int r0, RL, n, RR, r1;
   int64_t N;
   const double* f;
   double* x;
-  double* W;            // N: current direction, published each step
-  double* Q;            // r0 x (n RR) x (r0 n): folded operator per slice
+  void* W;              // N, working precision: current direction, published each step
+  double* Q;            // r0 x (n RR) x (r0 n): folded operator per slice (FP64)
+  void* Qw;             // the same in the working precision (Q itself in FP64 mode)
   double* Pd1;          // G x (m + 1)
   double* Pd2;          // G x (m + 1)
   double* Pn;           // G x 2
   int m, max_iter, spw, ldv;
   double tol, eta;
+  double inner_tol;     // mixed mode: an inner cycle stops at this fraction of its start residual
   unsigned* bar;
   double* info;         // [iterations, converged, |g_k| / ||f||]
 };
@@ -99,16 +102,28 @@ __device__ __forceinline__ void wg_gemm(int M, int N, int K, double alpha, Strid
   __syncthreads();
 }
 
+template <typename U>
+__device__ __forceinline__ U ld_coh(const U* p);
+template <>
+__device__ __forceinline__ double ld_coh<double>(const double* p) {
+  return ld_coherent(p);
+}
+template <>
+__device__ __forceinline__ float ld_coh<float>(const float* p) {
+  const unsigned v = __hip_atomic_load(reinterpret_cast<unsigned*>(const_cast<float*>(p)),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(float, v);
+}
+
 // acc[q] += sum_k t[q * K + k] pr[k] over k = part, part + P, ... < K for
 // q < NI (t in LDS, pr in global memory); loads issued U at a time.
-template <int NI>
-__device__ __forceinline__ void row_dots(const double* __restrict__ pr,
-                                         const double* __restrict__ t, int K, int part, int P,
-                                         double* acc) {
+template <int NI, typename E>
+__device__ __forceinline__ void row_dots(const E* __restrict__ pr, const E* __restrict__ t, int K,
+                                         int part, int P, E* acc) {
   constexpr int U = 16;
   int kb = part;
   for (; kb + P * (U - 1) < K; kb += P * U) {
-    double pv[U];
+    E pv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) pv[u] = pr[kb + P * u];
 #pragma unroll
@@ -118,7 +133,7 @@ __device__ __forceinline__ void row_dots(const double* __restrict__ pr,
     }
   }
   for (; kb < K; kb += P) {
-    const double p = pr[kb];
+    const E p = pr[kb];
 #pragma unroll
     for (int q = 0; q < NI; ++q) acc[q] = fma(t[q * K + kb], p, acc[q]);
   }
@@ -126,28 +141,27 @@ __device__ __forceinline__ void row_dots(const double* __restrict__ pr,
 
 // TM x TN tile of C = alpha A B with A (M x K, row-major, lda) streamed from
 // global memory through As and B (Kp x Np, zero-padded, row stride Np)
-// already in LDS.
-template <int TM, int TN>
-__device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int K, double alpha,
-                                               const double* __restrict__ A, int lda,
-                                               const double* __restrict__ Bl, int Np,
-                                               double* __restrict__ C, int ldc,
-                                               double* __restrict__ As) {
+// already in LDS; all operands of element type E.
+template <int TM, int TN, typename E>
+__device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int K, E alpha,
+                                               const E* __restrict__ A, int lda,
+                                               const E* __restrict__ Bl, int Np,
+                                               E* __restrict__ C, int ldc, E* __restrict__ As) {
   constexpr int KC = 16, NA = TM * KC / 256, CG = TN / 4;
   const int m0 = tm * TM, n0 = tn * TN;
   const int tid = threadIdx.x, tr = tid / CG, tc = tid % CG;
-  double acc[4][4];
+  E acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  double ra[NA];
+    for (int j = 0; j < 4; ++j) acc[i][j] = E(0);
+  E ra[NA];
   auto load = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
       const int e = tid + t * 256, mm = e / KC, kk = e % KC;
       const int gm = m0 + mm, gk = k0 + kk;
-      ra[t] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
+      ra[t] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : E(0);
     }
   };
   load(0);
@@ -162,15 +176,15 @@ __device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int
     if (k0 + KC < K) load(k0 + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
-      double a[4], b[4];
+      E av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk * (TM + 1) + tr * 4 + i];
+      for (int i = 0; i < 4; ++i) av[i] = As[kk * (TM + 1) + tr * 4 + i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bl[(k0 + kk) * Np + n0 + tc + CG * j];
+      for (int j = 0; j < 4; ++j) bv[j] = Bl[(k0 + kk) * Np + n0 + tc + CG * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
     }
   }
 #pragma unroll
@@ -185,116 +199,170 @@ __device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int
   }
 }
 
+// Geometry of one workgroup's share, and its LDS regions (doubles first, the
+// working-precision basis last).
+struct Ctx {
+  int G, b, tid, lane;
+  int m, ldv, nr1, nr0, nRR, a0, a1, nloc, K3;
+  int64_t e0;
+  int TNf, Kp, Np;
+  double* As;     // GEMM staging (kAsDoubles doubles of room)
+  double* Bs;     // whole right operand of the first product (kBFull doubles of room)
+  double* Ts;     // n RR x r1 product (FP64 room)
+  double* Yd;     // ldv: FP64 residual output
+  double* Hpk;    // rotated Hessenberg, column c at c (c + 1) / 2
+  double* hcol;
+  double* h2;
+  double* cs;
+  double* sn;
+  double* gv;
+  void* Vl;       // (m + 1) x ldv, working precision
+};
+
+// y (own slices) = (PhiL (x) A (x) PhiR)(alpha v) in precision E, into the LDS
+// row `out`; v is read with coherent loads.  Qe and phiRe are the operator in
+// precision E.  fullB: the whole right operand fits in Bs.
+template <typename E>
+__device__ void apply_slices(const SArgs& a, const Ctx& c, const E* Qe, const E* phiRe,
+                             const E* v, E alpha, E* out, bool fullB) {
+  const int tid = c.tid;
+  E* As = reinterpret_cast<E*>(c.As);
+  E* Bs = reinterpret_cast<E*>(c.Bs);
+  E* Ts = reinterpret_cast<E*>(c.Ts);
+  if (fullB) {
+    __syncthreads();
+    for (int e = tid; e < c.Kp * c.Np; e += kThreads) {
+      const int k = e / c.Np, cc = e % c.Np;
+      Bs[e] = (k < c.nr0 && cc < a.r1) ? ld_coh<E>(v + (int64_t)k * a.r1 + cc) : E(0);
+    }
+    __syncthreads();
+  }
+  for (int s = c.a0; s < c.a1; ++s) {
+    const E* Qa = Qe + (int64_t)s * c.nRR * c.nr0;
+    if (fullB) {
+      if (c.TNf == 32) {
+        for (int t = 0; t < cdiv(c.nRR, 128); ++t)
+          gemm_tile_ldsb<128, 32, E>(t, 0, c.nRR, a.r1, c.nr0, alpha, Qa, c.nr0, Bs, c.Np, Ts,
+                                     a.r1, As);
+      } else {
+        const int tn = c.Np / 64;
+        for (int t = 0; t < cdiv(c.nRR, 64) * tn; ++t)
+          gemm_tile_ldsb<64, 64, E>(t / tn, t % tn, c.nRR, a.r1, c.nr0, alpha, Qa, c.nr0, Bs,
+                                    c.Np, Ts, a.r1, As);
+      }
+      __syncthreads();
+    } else {
+      // FP64 only (the host plan requires fullB in the mixed mode)
+      wg_gemm<true>(c.nRR, a.r1, c.nr0, (double)alpha,
+                    Strided{reinterpret_cast<const double*>(Qa), c.nr0, 1},
+                    Strided{reinterpret_cast<const double*>(v), a.r1, 1},
+                    reinterpret_cast<double*>(Ts), a.r1, 1, c.As, c.Bs);
+    }
+    // y[i][c] = sum_k T[i][k] PhiR[c][k]: P lanes per output row c, partial
+    // sums combined across the P lanes by a fixed butterfly.
+    int P = 64;
+    while (P > 1 && P * a.r1 > kThreads) P >>= 1;
+    const int rows = kThreads / P, part = tid % P;
+    E* ys = out + (s - c.a0) * c.nr1;
+    for (int c0 = 0; c0 < a.r1; c0 += rows) {
+      const int cr = c0 + tid / P;
+      for (int i0 = 0; i0 < a.n; i0 += 4) {
+        const int ni = min(4, a.n - i0);
+        E acc[4] = {E(0), E(0), E(0), E(0)};
+        if (cr < a.r1) {
+          const E* pr = phiRe + (int64_t)cr * c.K3;
+          const E* t2 = Ts + (int64_t)i0 * c.K3;
+          switch (ni) {
+            case 1: row_dots<1, E>(pr, t2, c.K3, part, P, acc); break;
+            case 2: row_dots<2, E>(pr, t2, c.K3, part, P, acc); break;
+            case 3: row_dots<3, E>(pr, t2, c.K3, part, P, acc); break;
+            default: row_dots<4, E>(pr, t2, c.K3, part, P, acc); break;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          for (int o = P >> 1; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+        if (part == 0 && cr < a.r1) {
+          for (int q = 0; q < ni; ++q) ys[(i0 + q) * a.r1 + cr] = acc[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The solve.  T is the working precision of the Krylov iterations; restart
+// residuals r = f - A x and x itself are always FP64.  With T = float each
+// restart cycle is one step of iterative refinement: the cycle solves
+// A d = r in FP32 to inner_tol (or to the global target) and x += d in FP64.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[4];
   __shared__ double bcast[4];
-  const int G = gridDim.x, b = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int m = a.m, ldv = a.ldv;
-  const int nr1 = a.n * a.r1, nr0 = a.n * a.r0, nRR = a.n * a.RR;
-  const int a0 = min(a.r0, b * a.spw), a1 = min(a.r0, a0 + a.spw);
-  const int nloc = (a1 - a0) * nr1;
-  const int64_t e0 = (int64_t)a0 * nr1;
-  const int K3 = a.RR * a.r1;
-
-  double* As = lds;
-  double* Bs = As + kAsDoubles;
-  double* Ts = Bs + kBsDoubles;                 // n RR x r1
-  double* Vl = Ts + (int64_t)nRR * a.r1;        // (m + 1) x ldv
-  double* Hpk = Vl + (int64_t)(m + 1) * ldv;    // rotated Hessenberg, column c at c (c + 1) / 2
-  double* hcol = Hpk + m * (m + 1) / 2;
-  double* h2 = hcol + (m + 2);
-  double* cs = h2 + (m + 2);
-  double* sn = cs + (m + 2);
-  double* gv = sn + (m + 2);
+  constexpr bool kMixed = sizeof(T) < sizeof(double);
+  Ctx c;
+  c.G = gridDim.x;
+  c.b = blockIdx.x;
+  c.tid = threadIdx.x;
+  c.lane = c.tid & 63;
+  c.m = a.m;
+  c.ldv = a.ldv;
+  c.nr1 = a.n * a.r1;
+  c.nr0 = a.n * a.r0;
+  c.nRR = a.n * a.RR;
+  c.a0 = min(a.r0, c.b * a.spw);
+  c.a1 = min(a.r0, c.a0 + a.spw);
+  c.nloc = (c.a1 - c.a0) * c.nr1;
+  c.e0 = (int64_t)c.a0 * c.nr1;
+  c.K3 = a.RR * a.r1;
+  c.TNf = a.r1 <= 32 ? 32 : 64;
+  c.Kp = cdiv(c.nr0, 16) * 16;
+  c.Np = cdiv(a.r1, c.TNf) * c.TNf;
+  c.As = lds;
+  c.Bs = c.As + kAsDoubles;
+  c.Ts = c.Bs + kBsDoubles;
+  c.Yd = c.Ts + (int64_t)c.nRR * a.r1;
+  c.Hpk = c.Yd + c.ldv;
+  c.hcol = c.Hpk + c.m * (c.m + 1) / 2;
+  c.h2 = c.hcol + (c.m + 2);
+  c.cs = c.h2 + (c.m + 2);
+  c.sn = c.cs + (c.m + 2);
+  c.gv = c.sn + (c.m + 2);
+  c.Vl = c.gv + (c.m + 2);
+  const int G = c.G, b = c.b, tid = c.tid, lane = c.lane, m = c.m, ldv = c.ldv;
+  const int nloc = c.nloc;
+  const int64_t e0 = c.e0;
+  double* Hpk = c.Hpk;
+  double* hcol = c.hcol;
+  double* h2 = c.h2;
+  double* cs = c.cs;
+  double* sn = c.sn;
+  double* gv = c.gv;
+  T* Vl = reinterpret_cast<T*>(c.Vl);
+  T* W = reinterpret_cast<T*>(a.W);
+  const T* Qw = reinterpret_cast<const T*>(a.Qw);
+  const T* phiRw = reinterpret_cast<const T*>(a.phiRw);
+  const bool fullB64 = (int64_t)c.Kp * c.Np <= kBFull;
+  const bool fullBw = (int64_t)c.Kp * c.Np * sizeof(T) <= (int64_t)kBFull * sizeof(double);
   unsigned target = 0;
-#ifdef KRYLOV_PROF
-  long long pacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  long long pt = wall_clock64();
-#define PMARK(k) do { if (tid == 0) { const long long t_ = wall_clock64(); pacc[k] += t_ - pt; pt = t_; } } while (0)
-#else
-#define PMARK(k) do { } while (0)
-#endif
 
   // Q_a for the own slices (once per solve; read back by this workgroup only)
-  for (int s = a0; s < a1; ++s) {
-    double* Qa = a.Q + (int64_t)s * nRR * nr0;
+  for (int s = c.a0; s < c.a1; ++s) {
+    double* Qa = a.Q + (int64_t)s * c.nRR * c.nr0;
     for (int j = 0; j < a.n; ++j)
-      wg_gemm<false>(nRR, a.r0, a.RL, 1.0, Strided{a.Ap + j, (int64_t)a.RL * a.n, a.n},
-                     Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1}, Qa + j, nr0, a.n, As,
-                     Bs);
+      wg_gemm<false>(c.nRR, a.r0, a.RL, 1.0, Strided{a.Ap + j, (int64_t)a.RL * a.n, a.n},
+                     Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1}, Qa + j, c.nr0, a.n,
+                     c.As, c.Bs);
+    if (kMixed) {
+      T* Qt = reinterpret_cast<T*>(a.Qw) + (int64_t)s * c.nRR * c.nr0;
+      for (int e = tid; e < c.nRR * c.nr0; e += kThreads) Qt[e] = (T)Qa[e];
+      __syncthreads();
+    }
   }
 
-  // y (own slices) = (PhiL (x) A (x) PhiR)(alpha v) into LDS row `out`; v is
-  // read with coherent loads.
-  // Whole right operand of the first product in LDS when it fits (one round
-  // trip for the coherent loads), else streamed chunk by chunk.
-  const int TNf = a.r1 <= 32 ? 32 : 64;
-  const int Kp = cdiv(nr0, 16) * 16, Np = cdiv(a.r1, TNf) * TNf;
-  const bool fullB = (int64_t)Kp * Np <= kBFull;
-  auto apply = [&](const double* v, double alpha, double* out) {
-    if (fullB) {
-      __syncthreads();
-      for (int e = tid; e < Kp * Np; e += kThreads) {
-        const int k = e / Np, c = e % Np;
-        Bs[e] = (k < nr0 && c < a.r1) ? ld_coherent(v + (int64_t)k * a.r1 + c) : 0.0;
-      }
-      __syncthreads();
-    }
-    for (int s = a0; s < a1; ++s) {
-      const double* Qa = a.Q + (int64_t)s * nRR * nr0;
-      if (fullB) {
-        if (TNf == 32) {
-          for (int t = 0; t < cdiv(nRR, 128); ++t)
-            gemm_tile_ldsb<128, 32>(t, 0, nRR, a.r1, nr0, alpha, Qa, nr0, Bs, Np, Ts, a.r1, As);
-        } else {
-          const int tn = Np / 64;
-          for (int t = 0; t < cdiv(nRR, 64) * tn; ++t)
-            gemm_tile_ldsb<64, 64>(t / tn, t % tn, nRR, a.r1, nr0, alpha, Qa, nr0, Bs, Np, Ts,
-                                   a.r1, As);
-        }
-        __syncthreads();
-      } else {
-        wg_gemm<true>(nRR, a.r1, nr0, alpha, Strided{Qa, nr0, 1}, Strided{v, a.r1, 1}, Ts, a.r1,
-                      1, As, Bs);
-      }
-      PMARK(0);
-      // y[i][c] = sum_k T[i][k] PhiR[c][k]: P lanes per output row c, partial
-      // sums combined across the P lanes by a fixed butterfly.
-      int P = 64;
-      while (P > 1 && P * a.r1 > kThreads) P >>= 1;
-      const int rows = kThreads / P, part = tid % P;
-      double* ys = out + (s - a0) * nr1;
-      for (int c0 = 0; c0 < a.r1; c0 += rows) {
-        const int c = c0 + tid / P;
-        for (int i0 = 0; i0 < a.n; i0 += 4) {
-          const int ni = min(4, a.n - i0);
-          double acc[4] = {0.0, 0.0, 0.0, 0.0};
-          if (c < a.r1) {
-            const double* pr = a.phiR + (int64_t)c * K3;
-            const double* t2 = Ts + (int64_t)i0 * K3;
-            switch (ni) {
-              case 1: row_dots<1>(pr, t2, K3, part, P, acc); break;
-              case 2: row_dots<2>(pr, t2, K3, part, P, acc); break;
-              case 3: row_dots<3>(pr, t2, K3, part, P, acc); break;
-              default: row_dots<4>(pr, t2, K3, part, P, acc); break;
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            for (int o = P >> 1; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
-          if (part == 0 && c < a.r1) {
-            for (int q = 0; q < ni; ++q) ys[(i0 + q) * a.r1 + c] = acc[q];
-          }
-        }
-      }
-      __syncthreads();
-      PMARK(2);
-    }
-  };
-  // out[i] = <Vl_i, Vl_w> over the chunk for i <= j (gs lanes per vector).
-  auto dots = [&](int j, const double* w, double* out) {
+  // Partial dots of w with V_0..V_j over the chunk (gs lanes per vector, FP64 sums).
+  auto dots = [&](int j, const T* w, double* out) {
     int gs = 64;
     while (gs > 1 && (j + 1) * gs > kThreads) gs >>= 1;
     const int per = kThreads / gs;
@@ -302,8 +370,8 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       const int i = i0 + tid / gs, p = tid % gs;
       double acc = 0.0;
       if (i <= j) {
-        const double* vi = Vl + (int64_t)i * ldv;
-        for (int e = p; e < nloc; e += gs) acc = fma(vi[e], w[e], acc);
+        const T* vi = Vl + (int64_t)i * ldv;
+        for (int e = p; e < nloc; e += gs) acc = fma((double)vi[e], (double)w[e], acc);
       }
       for (int o = gs >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if (p == 0 && i <= j) out[i] = acc;
@@ -337,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     }
     __syncthreads();
   };
-  // sum over workgroups of Pn[2 q + k] by wave 0 (fixed order), into bcast[k]
+  // sum over workgroups of Pn[2 q + k] by wave 0 (fixed order), into bcast[2 + k]
   auto gather_pn = [&](int k) {
     if (tid < 64) {
       double acc = 0.0;
@@ -346,20 +414,21 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       if (lane == 0) bcast[2 + k] = acc;
     }
   };
-  // w -= sum_i h[i] Vl_i over the chunk; returns this thread's ||w||^2 share
-  auto orth = [&](double* w, int j, const double* h) {
+  // w -= sum_i h[i] Vl_i over the chunk (FP64 arithmetic); returns this
+  // thread's ||w||^2 share
+  auto orth = [&](T* w, int j, const double* h) {
     double nn = 0.0;
     for (int e = tid; e < nloc; e += kThreads) {
-      double s0 = w[e], s1 = 0.0;
+      double s0 = (double)w[e], s1 = 0.0;
       int i = 0;
       for (; i + 1 <= j; i += 2) {
-        s0 -= h[i] * Vl[(int64_t)i * ldv + e];
-        s1 -= h[i + 1] * Vl[(int64_t)(i + 1) * ldv + e];
+        s0 -= h[i] * (double)Vl[(int64_t)i * ldv + e];
+        s1 -= h[i + 1] * (double)Vl[(int64_t)(i + 1) * ldv + e];
       }
-      if (i <= j) s0 -= h[i] * Vl[(int64_t)i * ldv + e];
-      const double r = s0 + s1;
+      if (i <= j) s0 -= h[i] * (double)Vl[(int64_t)i * ldv + e];
+      const T r = (T)(s0 + s1);
       w[e] = r;
-      nn = fma(r, r, nn);
+      nn = fma((double)r, (double)r, nn);
     }
     return nn;
   };
@@ -368,14 +437,15 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   bool conv = false;
   double fnorm = 0.0, tgt = -1.0, res_est = 0.0;
   while (true) {
-    // r = f - A x into Vl_0 and W (unnormalised), ||r||^2 and ||f||^2
-    apply(a.x, 1.0, Vl);
+    // r = f - A x in FP64 (x and the FP64 operator); r is rounded into Vl_0
+    // and W (unnormalised).  ||r||^2 and ||f||^2.
+    apply_slices<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd, fullB64);
     double rr = 0.0, ff = 0.0;
     for (int e = tid; e < nloc; e += kThreads) {
       const double fe = a.f[e0 + e];
-      const double r = fe - Vl[e];
-      Vl[e] = r;
-      a.W[e0 + e] = r;
+      const double r = fe - c.Yd[e];
+      Vl[e] = (T)r;
+      W[e0 + e] = (T)r;
       rr = fma(r, r, rr);
       ff = fma(fe, fe, ff);
     }
@@ -406,42 +476,38 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       conv = beta <= tgt;
       break;
     }
+    // an FP32 cycle only needs to reduce its own residual by inner_tol
+    const double cycle_tgt = kMixed ? fmax(tgt, a.inner_tol * beta) : tgt;
     for (int i = tid; i < m + 2; i += kThreads) gv[i] = i == 0 ? beta : 0.0;
     __syncthreads();
     double nu = beta;
     int j = 0;
     while (true) {
-      double* w = Vl + (int64_t)(j + 1) * ldv;
-      apply(a.W, 1.0 / nu, w);
+      T* w = Vl + (int64_t)(j + 1) * ldv;
+      apply_slices<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w, fullBw);
       // normalise V_j (its norm is known now), first-pass dots
       {
         const double inv = 1.0 / nu;
-        double* vj = Vl + (int64_t)j * ldv;
-        for (int e = tid; e < nloc; e += kThreads) vj[e] *= inv;
+        T* vj = Vl + (int64_t)j * ldv;
+        for (int e = tid; e < nloc; e += kThreads) vj[e] = (T)((double)vj[e] * inv);
         __syncthreads();
         dots(j, w, a.Pd1 + (int64_t)b * (m + 1));
       }
-      PMARK(3);
       grid_sync(a.bar, target);
-      PMARK(4);
       gather(a.Pd1, j, hcol);
       orth(w, j, hcol);
       __syncthreads();
       dots(j, w, a.Pd2 + (int64_t)b * (m + 1));
-      PMARK(5);
       grid_sync(a.bar, target);
-      PMARK(4);
       gather(a.Pd2, j, h2);
       {
         double nn = orth(w, j, h2);
         for (int i = tid; i <= j; i += kThreads) hcol[i] += h2[i];
-        for (int e = tid; e < nloc; e += kThreads) a.W[e0 + e] = w[e];
+        for (int e = tid; e < nloc; e += kThreads) W[e0 + e] = w[e];
         nn = wg_sum(nn, red);
         if (tid == 0) a.Pn[2 * b] = nn;
       }
-      PMARK(5);
       grid_sync(a.bar, target);
-      PMARK(4);
       gather_pn(0);
       __syncthreads();
       // norm, Hessenberg column, Givens rotation (every workgroup, same order)
@@ -454,25 +520,25 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
         }
         const double p = hcol[j], q = nrm;
         const double rho = sqrt(p * p + q * q);
-        const double c = rho > 0.0 ? p / rho : 1.0, sg = rho > 0.0 ? q / rho : 0.0;
-        cs[j] = c;
+        const double cc = rho > 0.0 ? p / rho : 1.0, sg = rho > 0.0 ? q / rho : 0.0;
+        cs[j] = cc;
         sn[j] = sg;
         hcol[j] = rho;
         gv[j + 1] = -sg * gv[j];
-        gv[j] = c * gv[j];
+        gv[j] = cc * gv[j];
         double* col = Hpk + j * (j + 1) / 2;
         for (int i = 0; i <= j; ++i) col[i] = hcol[i];
         bcast[0] = nrm;
         bcast[1] = fabs(gv[j + 1]);
       }
       __syncthreads();
-      PMARK(6);
       nu = bcast[0];
       res_est = bcast[1];
       ++j;
       ++total;
-      if (res_est <= tgt) {
-        conv = true;
+      if (res_est <= cycle_tgt) {
+        // FP64: the estimate is trusted.  Mixed: the next FP64 residual decides.
+        conv = !kMixed;
         break;
       }
       if (j >= m || total >= a.max_iter || !(nu > 0.0)) break;
@@ -494,16 +560,12 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     __syncthreads();
     for (int e = tid; e < nloc; e += kThreads) {
       double acc = a.x[e0 + e];
-      for (int i = 0; i < j; ++i) acc = fma(h2[i], Vl[(int64_t)i * ldv + e], acc);
+      for (int i = 0; i < j; ++i) acc = fma(h2[i], (double)Vl[(int64_t)i * ldv + e], acc);
       a.x[e0 + e] = acc;
     }
     if (conv || total >= a.max_iter) break;
     grid_sync(a.bar, target);
   }
-#ifdef KRYLOV_PROF
-  if (b == 0 && tid == 0)
-    for (int k = 0; k < 8; ++k) a.info[3 + k] = (double)pacc[k] * 10.0;   // ns at 100 MHz
-#endif
   if (b == 0 && tid == 0) {
     a.info[0] = (double)total;
     a.info[1] = conv ? 1.0 : 0.0;
@@ -519,7 +581,12 @@ struct DevInfo {
 constexpr int kMaxDev = 64;
 std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
 
-// Device properties, and the kernel's LDS attribute raised once per device
+const void* kernel_ptr(bool mixed) {
+  return mixed ? reinterpret_cast<const void*>(gmres_slices_kernel<float>)
+               : reinterpret_cast<const void*>(gmres_slices_kernel<double>);
+}
+
+// Device properties, and the kernels' LDS attribute raised once per device
 // and process.
 DevInfo dev_info() {
   static DevInfo di[kMaxDev];
@@ -535,8 +602,9 @@ DevInfo dev_info() {
     TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     TT_REQUIRE(coop != 0, "device does not support cooperative launches");
     TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(gmres_slices_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
+    for (bool mixed : {false, true})
+      TT_HIP(hipFuncSetAttribute(kernel_ptr(mixed), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 d.lds_max - 1024));
     di[dev] = d;
     ready[dev] = true;
   }
@@ -559,30 +627,47 @@ struct Plan {
   size_t lds_bytes = 0;
 };
 
-size_t lds_doubles(const KrylovShape& sh, int m, int ldv) {
-  return (size_t)kAsDoubles + kBsDoubles + (size_t)sh.n * sh.RR * sh.r1 + (size_t)(m + 1) * ldv +
-         (size_t)m * (m + 1) / 2 + 5 * (size_t)(m + 2) + 32;
+size_t lds_bytes_for(const KrylovShape& sh, int m, int ldv, bool mixed) {
+  const size_t dbl = (size_t)kAsDoubles + kBsDoubles + (size_t)sh.n * sh.RR * sh.r1 + ldv +
+                     (size_t)m * (m + 1) / 2 + 5 * (size_t)(m + 2) + 32;
+  return dbl * sizeof(double) + (size_t)(m + 1) * ldv * (mixed ? sizeof(float) : sizeof(double));
 }
 
 // Workgroups, slices per workgroup and the restart length that fits in LDS
-// (the largest m <= restart, at least 2); G == 0 when nothing fits.
-Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes) {
+// (the largest m <= restart, at least 2); G == 0 when nothing fits.  The
+// mixed kernel also needs the whole FP32 right operand of its first product
+// in LDS.
+Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mixed) {
   Plan p;
   const int cap = std::max(1, grid_cap());
   p.spw = (sh.r0 + cap - 1) / cap;
   p.G = (sh.r0 + p.spw - 1) / p.spw;
   const int nloc = p.spw * sh.n * sh.r1;
   p.ldv = nloc + ((nloc % 2 == 0) ? 1 : 0);
-  const size_t limit = (size_t)std::max(0, lds_limit_bytes - 1024) / sizeof(double);
+  if (mixed) {
+    const int TNf = sh.r1 <= 32 ? 32 : 64;
+    const int64_t Kp = cdiv((int64_t)sh.n * sh.r0, 16) * 16, Np = cdiv(sh.r1, TNf) * TNf;
+    if (Kp * Np * (int64_t)sizeof(float) > (int64_t)kBFull * (int64_t)sizeof(double)) {
+      p.G = 0;
+      return p;
+    }
+  }
+  const size_t limit = (size_t)std::max(0, lds_limit_bytes - 1024);
   int m = std::min(restart, kMaxRestart);
-  while (m >= 2 && lds_doubles(sh, m, p.ldv) > limit) --m;
+  while (m >= 2 && lds_bytes_for(sh, m, p.ldv, mixed) > limit) --m;
   if (m < 2) {
     p.G = 0;
     return p;
   }
   p.m = m;
-  p.lds_bytes = lds_doubles(sh, m, p.ldv) * sizeof(double);
+  p.lds_bytes = lds_bytes_for(sh, m, p.ldv, mixed);
   return p;
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
 }
 
 }  // namespace
@@ -599,10 +684,10 @@ int krylov_grid() { return grid_cap(); }
 
 void krylov_set_thread_cap(int cap) { t_cap_override = cap > 0 ? cap : 0; }
 
-bool krylov_fits(const KrylovShape& sh, int restart) {
+bool krylov_fits(const KrylovShape& sh, int restart, bool mixed) {
   if (restart < 2 || sh.r0 <= 0 || sh.r1 <= 0 || sh.n <= 0 || sh.RL <= 0 || sh.RR <= 0)
     return false;
-  return make_plan(sh, restart, dev_info().lds_max).G > 0;
+  return make_plan(sh, restart, dev_info().lds_max, mixed).G > 0;
 }
 
 size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
@@ -611,25 +696,31 @@ size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
   const int spw = (sh.r0 + cap - 1) / cap;
   const int64_t G = (sh.r0 + spw - 1) / spw;
   const int64_t m = std::min(restart, kMaxRestart);
+  const int64_t nq = (int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n;
+  const int64_t nr = (int64_t)sh.r1 * sh.RR * sh.r1;
   int64_t need = 0;
-  need += N + 32;                                                  // W
-  need += (int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n + 32;       // Q
-  need += 2 * (G * (m + 1) + 32);                    // Pd1, Pd2
-  need += 2 * G + 32;                                // Pn
-  need += 64;                                        // barrier counter
+  need += N + 32;                    // W (either precision)
+  need += nq + 32;                   // Q
+  need += (nq + 1) / 2 + 32;         // Q in FP32 (mixed)
+  need += (nr + 1) / 2 + 32;         // PhiR in FP32 (mixed)
+  need += 2 * (G * (m + 1) + 32);    // Pd1, Pd2
+  need += 2 * G + 32;                // Pn
+  need += 64;                        // barrier counter
   return (size_t)need + 8 * 32;
 }
 
 bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, const double* Ap,
                   const double* phiR, const double* f, double* x, int restart, int max_iter,
                   double tol, double eta, double* ws, size_t ws_doubles, double* info,
-                  int /*grid*/) {
+                  int /*grid*/, bool mixed, double inner_tol) {
   TT_REQUIRE(max_iter >= 0, "Krylov solve: negative iteration limit");
   const DevInfo di = dev_info();
-  const Plan p = make_plan(sh, restart, di.lds_max);
+  const Plan p = make_plan(sh, restart, di.lds_max, mixed);
   TT_REQUIRE(p.G > 0, "Krylov solve: local system too large for the LDS-resident basis");
   TT_REQUIRE(ws_doubles >= krylov_ws_doubles(sh, restart, 0), "Krylov solve: workspace too small");
   const int64_t N = (int64_t)sh.r0 * sh.n * sh.r1;
+  const int64_t nq = (int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n;
+  const int64_t nr = (int64_t)sh.r1 * sh.RR * sh.r1;
   double* cur = ws;
   auto take = [&](int64_t count) {
     double* r = cur;
@@ -649,7 +740,11 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.f = f;
   a.x = x;
   a.W = take(N);
-  a.Q = take((int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n);
+  a.Q = take(nq);
+  float* q32 = reinterpret_cast<float*>(take((nq + 1) / 2));
+  float* r32 = reinterpret_cast<float*>(take((nr + 1) / 2));
+  a.Qw = mixed ? static_cast<void*>(q32) : static_cast<void*>(a.Q);
+  a.phiRw = mixed ? static_cast<const void*>(r32) : static_cast<const void*>(phiR);
   a.Pd1 = take((int64_t)p.G * (p.m + 1));
   a.Pd2 = take((int64_t)p.G * (p.m + 1));
   a.Pn = take(2 * (int64_t)p.G);
@@ -661,14 +756,20 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.ldv = p.ldv;
   a.tol = tol;
   a.eta = eta;
+  a.inner_tol = inner_tol;
   a.info = info;
   TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
 
   int per_cu = 0;
-  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(gmres_slices_kernel), kThreads, p.lds_bytes));
+  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_ptr(mixed), kThreads,
+                                                      p.lds_bytes));
   TT_REQUIRE((int64_t)per_cu * di.cus >= p.G, "Krylov solve: grid exceeds co-resident capacity");
 
+  if (mixed) {
+    ++g_launches;
+    to_f32_kernel<<<(int)std::min<int64_t>(1024, (nr + 255) / 256), 256, 0, s>>>(phiR, r32, nr);
+    TT_HIP(hipGetLastError());
+  }
   fill(s, barslot, 1, 0.0);
   ++g_launches;
   hipEvent_t pe = nullptr;
@@ -676,15 +777,15 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   void* args[] = {&a};
   {
     std::lock_guard<std::mutex> lock(g_dev_mu);
-    TT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gmres_slices_kernel),
-                                      dim3(p.G), dim3(kThreads), args, p.lds_bytes, s));
+    TT_HIP(hipLaunchCooperativeKernel(kernel_ptr(mixed), dim3(p.G), dim3(kThreads), args,
+                                      p.lds_bytes, s));
   }
   if (pe) g_probe->end(s);
   return pe != nullptr;
 }
 
-int krylov_restart(const KrylovShape& sh, int restart) {
-  const Plan p = make_plan(sh, restart, dev_info().lds_max);
+int krylov_restart(const KrylovShape& sh, int restart, bool mixed) {
+  const Plan p = make_plan(sh, restart, dev_info().lds_max, mixed);
   return p.G > 0 ? p.m : 0;
 }
 

@@ -64,6 +64,7 @@ struct Solver {
   std::vector<char> kry_pending;
   std::vector<int> kry_slot;
   std::vector<LocalOp> kry_op;
+  std::vector<char> kry_mixed;
   int64_t launch_acc = 0;
 
   ~Solver();

@@ -258,6 +258,8 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   lso.restart = o->gmres_restart > 0 ? o->gmres_restart : 80;
   lso.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
   lso.eta = 0.0;
+  TT_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 or 1");
+  lso.mixed = o->precision == 1;
   // identity operator (explicit mode right-hand side)
   Id.d = d;
   Id.m = n;
@@ -319,6 +321,7 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   kry_pending.assign(d, 0);
   kry_slot.assign(d, -1);
   kry_op.assign(d, LocalOp{});
+  kry_mixed.assign(d, 0);
   Bump real;
   real.base = (char*)mem;
   real.cap = mem_bytes;
@@ -420,6 +423,7 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
     kry_pending[k] = 1;
     kry_slot[k] = lr.probe_slot;
     kry_op[k] = xh;
+    kry_mixed[k] = lr.mixed ? 1 : 0;
   } else {
     st.local_iters += lr.iterations;
   }
@@ -569,7 +573,7 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
       if (!kry_pending[k]) continue;
       const int it = (int)h_kry[3 * k];
       st.local_iters += it;
-      krylov_probe_amend(kry_op[k], lso.restart, it, kry_slot[k]);
+      krylov_probe_amend(kry_op[k], lso.restart, it, kry_slot[k], kry_mixed[k] != 0);
       kry_pending[k] = 0;
     }
     ++sweeps;

@@ -61,7 +61,7 @@ class TTLocal(ctypes.Structure):
 class TTSolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("direct_max", ctypes.c_int32)]
+                ("direct_max", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class TTSolveInfo(ctypes.Structure):
@@ -79,7 +79,7 @@ class TTSolverOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int32), ("rhs_mode", ctypes.c_int32),
                 ("rhs_rmax", ctypes.c_int32), ("local_tol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int32), ("gmres_max_iter", ctypes.c_int32),
-                ("direct_max", ctypes.c_int32)]
+                ("direct_max", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class TTProbeStats(ctypes.Structure):
@@ -276,7 +276,8 @@ def tt_dot(a: DeviceTT, b: DeviceTT) -> float:
 
 
 def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
-                   max_iter: int = 1000, restart: int = 80, direct_max: int = 256):
+                   max_iter: int = 1000, restart: int = 80, direct_max: int = 256,
+                   precision: int = 0):
     """Solve the projected local system; tensors are float64 CUDA tensors.
 
     phiL [ra, RL, ra], A [RL, n, n, RR], phiR [rc, RR, rc], f/x0 [ra, n, rc].
@@ -289,7 +290,7 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
     tensors = [t.contiguous() for t in (phiL, A, phiR, f)]
     x = x0.contiguous().clone()
     sysd = TTLocal(ra, RL, m, n, RR, rc, *[ctypes.c_void_p(t.data_ptr()) for t in tensors])
-    opts = TTSolveOpts(method, tol, max_iter, restart, direct_max)
+    opts = TTSolveOpts(method, tol, max_iter, restart, direct_max, precision)
     nbytes = lib().tt_local_solve_workspace(ctypes.byref(sysd), ctypes.byref(opts))
     ws = _workspace(nbytes)
     info = TTSolveInfo()
@@ -332,13 +333,13 @@ class Solver:
                  k0: float = 1.0, tol: float = 1e-8, rmax: int = 32, kick: int = 4,
                  max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  local_tol: float = 0.0, gmres_restart: int = 80, gmres_max_iter: int = 2000,
-                 direct_max: int = 256):
+                 direct_max: int = 256, precision: int = 0):
         self._hold = (H, SF, F_core0, cF, psi0)
         prob = TTProblem(H.desc(), SF.desc(), ctypes.c_void_p(F_core0.data_ptr()), cF.desc(),
                          psi0.desc(), float(k0))
         opts = TTSolverOpts(float(tol), int(rmax), int(kick), int(max_sweeps), int(rhs_mode),
                             int(rhs_rmax), float(local_tol), int(gmres_restart),
-                            int(gmres_max_iter), int(direct_max))
+                            int(gmres_max_iter), int(direct_max), int(precision))
         h = ctypes.c_void_p()
         _check(lib().tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h

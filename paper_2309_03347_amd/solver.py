@@ -65,7 +65,7 @@ def joint_rhs_operator(S, F, tol: float = 1e-13):
 class KeffSolver:
     def __init__(self, wl, rmax: Optional[int] = None, tol: Optional[float] = None,
                  kick: int = 4, max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
-                 direct_max: int = 256, gmres_restart: int = 80, ops=None):
+                 direct_max: int = 256, gmres_restart: int = 80, ops=None, precision: int = 0):
         import torch
         self.wl = wl
         self.rmax = wl.rmax if rmax is None else rmax
@@ -84,7 +84,7 @@ class KeffSolver:
                                     tol=self.tol, rmax=self.rmax, kick=kick,
                                     max_sweeps=max_sweeps, rhs_mode=rhs_mode,
                                     rhs_rmax=rhs_rmax, direct_max=direct_max,
-                                    gmres_restart=gmres_restart)
+                                    gmres_restart=gmres_restart, precision=precision)
         self.history: List[StepRecord] = []
 
     @property

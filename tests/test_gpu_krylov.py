@@ -1,5 +1,7 @@
-"""Persistent GMRES local solve (method 2) against a dense solve and against
-the per-stage launch path (method 4) on the same systems.
+"""Persistent GMRES local solve (method 2, FP64 and mixed) against a dense
+solve and against the per-stage launch path (method 4) on the same systems.
+The mixed solve runs its Arnoldi cycles in FP32 and refines the FP64
+residual, so it is held to the FP64 bar.
 
 The local system is the Galerkin-projected operator of the alternating solve
 (Section 3.3): PhiL (x) A_k (x) PhiR acting on a core of shape [ra, n, rc].
@@ -53,20 +55,22 @@ def test_persistent_gmres_matches_dense(cuda, ra, RL, n, RR, rc, restart, diag):
     ref = np.linalg.solve(M, f)
     shape = (ra, n, rc)
     out = {}
-    for method in (2, 4):
-        print(f"local solve method={method} shape={(ra, RL, n, RR, rc)} restart={restart}", flush=True)
+    for method, precision in ((2, 0), (4, 0), (2, 1)):
+        print(f"local solve method={method} precision={precision} shape={(ra, RL, n, RR, rc)} "
+              f"restart={restart}", flush=True)
         x, info = native.tt_local_solve(_t(phiL), _t(A), _t(phiR), _t(f.reshape(shape)),
                                         _t(np.zeros(shape)), method=method, tol=1e-12,
-                                        max_iter=2000, restart=restart, direct_max=0)
+                                        max_iter=2000, restart=restart, direct_max=0,
+                                        precision=precision)
         x = x.cpu().numpy().reshape(-1)
         assert info["method"] == method
         assert info["converged"], info
         assert info["rel_res"] <= 1e-11, info
         assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref), info
-        out[method] = (x, info)
+        out[(method, precision)] = (x, info)
     # same arithmetic up to the order of the reductions
-    assert abs(out[2][1]["iterations"] - out[4][1]["iterations"]) <= 1
-    assert np.linalg.norm(out[2][0] - out[4][0]) <= 1e-10 * np.linalg.norm(ref)
+    assert abs(out[(2, 0)][1]["iterations"] - out[(4, 0)][1]["iterations"]) <= 1
+    assert np.linalg.norm(out[(2, 0)][0] - out[(4, 0)][0]) <= 1e-10 * np.linalg.norm(ref)
 
 
 def test_persistent_gmres_zero_rhs_and_exact_guess(cuda):

@@ -3,7 +3,9 @@
 The checker runs eq. k_eff_fixed_points with transport sweeps from the same
 (densified) iterate; the device path runs tt_power_step.  FP64 bar: k to
 1e-8 relative and the flux to 1e-6 relative L2 per step, with the rank cap
-lifted so that the truncation tolerance governs.
+lifted so that the truncation tolerance governs.  The mixed mode (FP32
+Arnoldi cycles refining the FP64 residual of each local system) is held to
+the same bar: its local solves still converge in FP64.
 """
 import numpy as np
 import pytest
@@ -19,11 +21,11 @@ def _unit(v):
     return v if v.sum() >= 0 else -v
 
 
-@pytest.mark.parametrize("rhs_mode", [0, 1])
-def test_power_steps_match_oracle_smallest(cuda, rhs_mode):
+@pytest.mark.parametrize("rhs_mode,precision", [(0, 0), (1, 0), (0, 1)])
+def test_power_steps_match_oracle_smallest(cuda, rhs_mode, precision):
     from paper_2309_03347_amd.solver import KeffSolver
     wl = W.config(0)                    # 8^3 nodes, 1 group, S2, tol 1e-10
-    s = KeffSolver(wl, rmax=64, rhs_mode=rhs_mode)
+    s = KeffSolver(wl, rmax=64, rhs_mode=rhs_mode, precision=precision)
     prob = sweep.Problem.from_workload(wl)
     psi = OT.full_vec(s.native.psi().cores())
     k = 1.0
@@ -50,12 +52,13 @@ def test_converged_k_matches_oracle_smallest(cuda):
     s.close()
 
 
-def test_power_steps_match_oracle_two_region(cuda):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_power_steps_match_oracle_two_region(cuda, precision):
     from paper_2309_03347_amd.solver import KeffSolver
     wl = W.inner_box(l=3, G=2, N=4, seed=21, rmax=64, tol=1e-10)
     # full rank on this grid, so tol governs; the cold start from the rank-1
     # psi_0 needs enough enrichment sweeps to reach it
-    s = KeffSolver(wl, rmax=256, kick=8, max_sweeps=60)
+    s = KeffSolver(wl, rmax=256, kick=8, max_sweeps=60, precision=precision)
     prob = sweep.Problem.from_workload(wl)
     psi = OT.full_vec(s.native.psi().cores())
     k = 1.0
