@@ -116,11 +116,12 @@ __device__ __forceinline__ float ld_coh<float>(const float* p) {
 }
 
 // acc[q] += sum_k t[q * K + k] pr[k] over k = part, part + P, ... < K for
-// q < NI (t in LDS, pr in global memory); loads issued U at a time.
+// q < NI (t in LDS, pr in global memory); loads issued U at a time, enough
+// in flight to cover the L2 latency of the stream.
 template <int NI, typename E>
 __device__ __forceinline__ void row_dots(const E* __restrict__ pr, const E* __restrict__ t, int K,
                                          int part, int P, E* acc) {
-  constexpr int U = 16;
+  constexpr int U = 32;
   int kb = part;
   for (; kb + P * (U - 1) < K; kb += P * U) {
     E pv[U];
@@ -230,10 +231,27 @@ __device__ void apply_slices(const SArgs& a, const Ctx& c, const E* Qe, const E*
   E* Bs = reinterpret_cast<E*>(c.Bs);
   E* Ts = reinterpret_cast<E*>(c.Ts);
   if (fullB) {
+    // coherent loads issued eight at a time before they are stored
+    constexpr int kB = 8;
+    const int total = c.Kp * c.Np;
     __syncthreads();
-    for (int e = tid; e < c.Kp * c.Np; e += kThreads) {
-      const int k = e / c.Np, cc = e % c.Np;
-      Bs[e] = (k < c.nr0 && cc < a.r1) ? ld_coh<E>(v + (int64_t)k * a.r1 + cc) : E(0);
+    for (int e0 = tid; e0 < total; e0 += kB * kThreads) {
+      E tmp[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + u * kThreads;
+        E val = E(0);
+        if (e < total) {
+          const int k = e / c.Np, cc = e % c.Np;
+          if (k < c.nr0 && cc < a.r1) val = ld_coh<E>(v + (int64_t)k * a.r1 + cc);
+        }
+        tmp[u] = val;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < total) Bs[e] = tmp[u];
+      }
     }
     __syncthreads();
   }
