@@ -208,6 +208,12 @@ typedef struct {
   int32_t direct_max;    /* local systems up to this size use dense LU */
   int32_t precision;     /* local GMRES: 0 FP64, 1 mixed (FP32 Arnoldi, FP64 refinement);
                             everything else in the step stays FP64 */
+  /* Sweeping while the rank cap binds (the truncation error then exceeds
+     tol, so the sweeps stop at stagnation instead of at tol): */
+  int32_t min_sweeps;    /* sweeps before the stagnation test may stop (0: 2) */
+  double cap_eta;        /* local solves reduce their residual by this factor (0: 1e-2) */
+  double stall;          /* stop when the largest local residual falls by less than this
+                            factor over a sweep (0: 0.5) */
 } tt_solver_opts;
 
 typedef struct {

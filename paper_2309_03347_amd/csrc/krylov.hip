@@ -140,6 +140,63 @@ __device__ __forceinline__ void row_dots(const E* __restrict__ pr, const E* __re
   }
 }
 
+// FP64 form of the same sums for the matrix-core kernel: lane `part` reads the
+// units part, part + P, ... of the row, a unit being W consecutive doubles
+// (W = 2: 16-byte loads, K even and pr 16-byte aligned).  The stream is read
+// in blocks of 32 / W units per lane, double-buffered: the loads of block
+// b + 1 are in flight while block b is multiplied.
+template <int NI, int W>
+__device__ __forceinline__ void row_dots_pipe(const double* __restrict__ pr,
+                                              const double* __restrict__ t, int K, int part,
+                                              int P, double* acc) {
+  constexpr int U = 32 / W;
+  typedef double V __attribute__((ext_vector_type(W)));
+  const V* pu = reinterpret_cast<const V*>(pr);
+  const int KU = K / W, S = P * U, span = P * (U - 1);
+  V pa[U], pb[U];
+  auto load = [&](V* buf, int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) buf[u] = pu[k0 + P * u];
+  };
+  auto mac = [&](const V* buf, int k0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = (k0 + P * u) * W;
+#pragma unroll
+      for (int q = 0; q < NI; ++q) {
+        const V tv = *reinterpret_cast<const V*>(t + q * K + k);
+#pragma unroll
+        for (int h = 0; h < W; ++h) acc[q] = fma(tv[h], buf[u][h], acc[q]);
+      }
+    }
+  };
+  int kb = part;
+  if (kb + span < KU) {
+    load(pa, kb);
+    while (true) {
+      int kn = kb + S;
+      bool more = kn + span < KU;
+      if (more) load(pb, kn);
+      mac(pa, kb);
+      kb = kn;
+      if (!more) break;
+      kn = kb + S;
+      more = kn + span < KU;
+      if (more) load(pa, kn);
+      mac(pb, kb);
+      kb = kn;
+      if (!more) break;
+    }
+  }
+  for (; kb < KU; kb += P) {
+    const V pv = pu[kb];
+#pragma unroll
+    for (int q = 0; q < NI; ++q)
+#pragma unroll
+      for (int h = 0; h < W; ++h) acc[q] = fma(t[q * K + kb * W + h], pv[h], acc[q]);
+  }
+}
+
 // TM x TN tile of C = alpha A B with A (M x K, row-major, lda) streamed from
 // global memory through As and B (Kp x Np, zero-padded, row stride Np)
 // already in LDS; all operands of element type E.
@@ -200,6 +257,35 @@ __device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int
   }
 }
 
+// MFMA form of the first product when a workgroup owns one slice (FP64).
+// The slice's folded operator Q_a (n RR <= 128 rows, n r0 <= 80 columns) is
+// the A operand of the FP64 16x16x4 matrix instruction, loaded straight into
+// the fragment registers; the right operand v ((n r0) x r1, r1 <= 64) is
+// staged in LDS in fragment order, one 64-double fragment per (k-step,
+// n-tile), so every fragment read is 64 consecutive doubles.  Lane l of a
+// wavefront holds A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[l / 16 + 4 r][l % 16], r < 4.  Wavefront w owns the m-tiles w and w + 4.
+constexpr int kMfmaKS = 20;      // k-steps of 4: n r0 <= 80
+constexpr int kMfmaMT = 2;       // m-tiles of 16 per wavefront
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct QFrag {
+  double q[kMfmaMT][kMfmaKS];
+};
+
+// Q_a (M1 x K1, row-major) into the wavefront's A fragments.
+__device__ __forceinline__ void load_qfrag(const double* __restrict__ Qa, int M1, int K1,
+                                           QFrag& f) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int mt = 0; mt < kMfmaMT; ++mt)
+#pragma unroll
+    for (int ks = 0; ks < kMfmaKS; ++ks) {
+      const int mm = 16 * (w + 4 * mt) + (l & 15), kk = 4 * ks + (l >> 4);
+      f.q[mt][ks] = (mm < M1 && kk < K1) ? Qa[(int64_t)mm * K1 + kk] : 0.0;
+    }
+}
+
 // Geometry of one workgroup's share, and its LDS regions (doubles first, the
 // working-precision basis last).
 struct Ctx {
@@ -219,6 +305,81 @@ struct Ctx {
   double* gv;
   void* Vl;       // (m + 1) x ldv, working precision
 };
+
+// ys[i][c] = sum_k Ts[i][k] PhiR[c][k] for one slice, k < RR r1: P lanes per
+// output row c, partial sums combined across the P lanes by a fixed butterfly.
+template <typename E>
+__device__ __forceinline__ void stage3(const SArgs& a, const Ctx& c, const E* phiRe, const E* Ts,
+                                       E* ys) {
+  const int tid = c.tid;
+  int P = 64;
+  while (P > 1 && P * a.r1 > kThreads) P >>= 1;
+  const int rows = kThreads / P, part = tid % P;
+  for (int c0 = 0; c0 < a.r1; c0 += rows) {
+    const int cr = c0 + tid / P;
+    for (int i0 = 0; i0 < a.n; i0 += 4) {
+      const int ni = min(4, a.n - i0);
+      E acc[4] = {E(0), E(0), E(0), E(0)};
+      if (cr < a.r1) {
+        const E* pr = phiRe + (int64_t)cr * c.K3;
+        const E* t2 = Ts + (int64_t)i0 * c.K3;
+        switch (ni) {
+          case 1: row_dots<1, E>(pr, t2, c.K3, part, P, acc); break;
+          case 2: row_dots<2, E>(pr, t2, c.K3, part, P, acc); break;
+          case 3: row_dots<3, E>(pr, t2, c.K3, part, P, acc); break;
+          default: row_dots<4, E>(pr, t2, c.K3, part, P, acc); break;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        for (int o = P >> 1; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+      if (part == 0 && cr < a.r1) {
+        for (int q = 0; q < ni; ++q) ys[(i0 + q) * a.r1 + cr] = acc[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The matrix-core kernel's form (FP64): every thread streams part of one row
+// of PhiR, P = 256 / r1 lanes per row (any P), and the P partial sums of a
+// row are added in a fixed order through LDS (red: 4 x 256 doubles).
+__device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const double* Ts,
+                                            double* ys) {
+  const int tid = c.tid, K = c.K3;
+  const int P = max(1, min(64, kThreads / a.r1)), rows = kThreads / P;
+  const bool w2 = (K % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.phiR) & 15) == 0);
+  double* red = c.As;
+  for (int c0 = 0; c0 < a.r1; c0 += rows) {
+    const int cr = c0 + tid / P, part = tid % P;
+    for (int i0 = 0; i0 < a.n; i0 += 2) {
+      const int ni = min(2, a.n - i0);
+      double acc[2] = {0.0, 0.0};
+      if (tid < rows * P && cr < a.r1) {
+        const double* pr = a.phiR + (int64_t)cr * K;
+        const double* t2 = Ts + (int64_t)i0 * K;
+        if (w2) {
+          if (ni == 2) row_dots_pipe<2, 2>(pr, t2, K, part, P, acc);
+          else row_dots_pipe<1, 2>(pr, t2, K, part, P, acc);
+        } else {
+          if (ni == 2) row_dots_pipe<2, 1>(pr, t2, K, part, P, acc);
+          else row_dots_pipe<1, 1>(pr, t2, K, part, P, acc);
+        }
+      }
+      red[tid] = acc[0];
+      red[kThreads + tid] = acc[1];
+      __syncthreads();
+      if (tid < rows && c0 + tid < a.r1) {
+        for (int q = 0; q < ni; ++q) {
+          double sum = 0.0;
+          for (int p = 0; p < P; ++p) sum += red[q * kThreads + tid * P + p];
+          ys[(i0 + q) * a.r1 + c0 + tid] = sum;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
 
 // y (own slices) = (PhiL (x) A (x) PhiR)(alpha v) in precision E, into the LDS
 // row `out`; v is read with coherent loads.  Qe and phiRe are the operator in
@@ -276,44 +437,77 @@ __device__ void apply_slices(const SArgs& a, const Ctx& c, const E* Qe, const E*
                     Strided{reinterpret_cast<const double*>(v), a.r1, 1},
                     reinterpret_cast<double*>(Ts), a.r1, 1, c.As, c.Bs);
     }
-    // y[i][c] = sum_k T[i][k] PhiR[c][k]: P lanes per output row c, partial
-    // sums combined across the P lanes by a fixed butterfly.
-    int P = 64;
-    while (P > 1 && P * a.r1 > kThreads) P >>= 1;
-    const int rows = kThreads / P, part = tid % P;
-    E* ys = out + (s - c.a0) * c.nr1;
-    for (int c0 = 0; c0 < a.r1; c0 += rows) {
-      const int cr = c0 + tid / P;
-      for (int i0 = 0; i0 < a.n; i0 += 4) {
-        const int ni = min(4, a.n - i0);
-        E acc[4] = {E(0), E(0), E(0), E(0)};
-        if (cr < a.r1) {
-          const E* pr = phiRe + (int64_t)cr * c.K3;
-          const E* t2 = Ts + (int64_t)i0 * c.K3;
-          switch (ni) {
-            case 1: row_dots<1, E>(pr, t2, c.K3, part, P, acc); break;
-            case 2: row_dots<2, E>(pr, t2, c.K3, part, P, acc); break;
-            case 3: row_dots<3, E>(pr, t2, c.K3, part, P, acc); break;
-            default: row_dots<4, E>(pr, t2, c.K3, part, P, acc); break;
-          }
-        }
+    stage3<E>(a, c, phiRe, Ts, out + (s - c.a0) * c.nr1);
+  }
+}
+
+// The same product for one slice per workgroup (FP64) on the matrix cores:
+// the A fragments of Q_a are loaded first (all in flight together, L2
+// resident after the first use), v is staged into Bs in fragment order while
+// they arrive, the first product goes into Ts and the second is stage3_pipe.
+__device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const double* v, double alpha,
+                                 double* out) {
+  const int tid = c.tid, l = c.lane, w = tid >> 6;
+  const int K1 = c.nr0, M1 = c.nRR, NT = cdiv(a.r1, 16), ksu = cdiv(K1, 4);
+  double* Bs = c.Bs;
+  double* Ts = c.Ts;
+  QFrag qf;
+  load_qfrag(a.Q + (int64_t)c.a0 * M1 * K1, M1, K1, qf);
+  {
+    constexpr int kB = 8;
+    const int total = ksu * NT * 64;
+    __syncthreads();
+    for (int e0 = tid; e0 < total; e0 += kB * kThreads) {
+      double tmp[kB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          for (int o = P >> 1; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
-        if (part == 0 && cr < a.r1) {
-          for (int q = 0; q < ni; ++q) ys[(i0 + q) * a.r1 + cr] = acc[q];
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + u * kThreads;
+        double val = 0.0;
+        if (e < total) {
+          const int frag = e >> 6, ln = e & 63, ks = frag / NT, nt = frag - ks * NT;
+          const int kk = 4 * ks + (ln >> 4), j = 16 * nt + (ln & 15);
+          if (kk < K1 && j < a.r1) val = ld_coherent(v + (int64_t)kk * a.r1 + j);
         }
+        tmp[u] = val;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < total) Bs[e] = tmp[u];
       }
     }
     __syncthreads();
   }
+  const bool second = 16 * (w + 4) < M1;     // the wavefront's second m-tile holds rows
+  for (int nt = 0; nt < NT; ++nt) {
+    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kMfmaKS; ++ks) {
+      if (ks < ksu) {
+        const double bv = Bs[(ks * NT + nt) * 64 + l];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qf.q[0][ks], bv, acc0, 0, 0, 0);
+        if (second) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qf.q[1][ks], bv, acc1, 0, 0, 0);
+      }
+    }
+    const int j = 16 * nt + (l & 15);
+    if (j < a.r1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m0 = 16 * w + (l >> 4) + 4 * r, m1 = m0 + 64;
+        if (m0 < M1) Ts[m0 * a.r1 + j] = alpha * acc0[r];
+        if (second && m1 < M1) Ts[m1 * a.r1 + j] = alpha * acc1[r];
+      }
+    }
+  }
+  __syncthreads();
+  stage3_pipe(a, c, Ts, out);
 }
 
 // The solve.  T is the working precision of the Krylov iterations; restart
 // residuals r = f - A x and x itself are always FP64.  With T = float each
 // restart cycle is one step of iterative refinement: the cycle solves
 // A d = r in FP32 to inner_tol (or to the global target) and x += d in FP64.
-template <typename T>
+template <typename T, bool MF>
 __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[4];
@@ -378,6 +572,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       __syncthreads();
     }
   }
+  static_assert(!(MF && kMixed), "the matrix-core path is FP64");
 
   // Partial dots of w with V_0..V_j over the chunk (gs lanes per vector, FP64 sums).
   auto dots = [&](int j, const T* w, double* out) {
@@ -457,7 +652,10 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   while (true) {
     // r = f - A x in FP64 (x and the FP64 operator); r is rounded into Vl_0
     // and W (unnormalised).  ||r||^2 and ||f||^2.
-    apply_slices<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd, fullB64);
+    if constexpr (MF)
+      apply_slice_mfma(a, c, a.x, 1.0, c.Yd);
+    else
+      apply_slices<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd, fullB64);
     double rr = 0.0, ff = 0.0;
     for (int e = tid; e < nloc; e += kThreads) {
       const double fe = a.f[e0 + e];
@@ -502,7 +700,11 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     int j = 0;
     while (true) {
       T* w = Vl + (int64_t)(j + 1) * ldv;
-      apply_slices<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w, fullBw);
+      if constexpr (MF)
+        apply_slice_mfma(a, c, reinterpret_cast<const double*>(W), 1.0 / nu,
+                         reinterpret_cast<double*>(w));
+      else
+        apply_slices<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w, fullBw);
       // normalise V_j (its norm is known now), first-pass dots
       {
         const double inv = 1.0 / nu;
@@ -599,9 +801,10 @@ struct DevInfo {
 constexpr int kMaxDev = 64;
 std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
 
-const void* kernel_ptr(bool mixed) {
-  return mixed ? reinterpret_cast<const void*>(gmres_slices_kernel<float>)
-               : reinterpret_cast<const void*>(gmres_slices_kernel<double>);
+const void* kernel_ptr(bool mixed, bool mf) {
+  if (mixed) return reinterpret_cast<const void*>(gmres_slices_kernel<float, false>);
+  return mf ? reinterpret_cast<const void*>(gmres_slices_kernel<double, true>)
+            : reinterpret_cast<const void*>(gmres_slices_kernel<double, false>);
 }
 
 // Device properties, and the kernels' LDS attribute raised once per device
@@ -620,9 +823,9 @@ DevInfo dev_info() {
     TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     TT_REQUIRE(coop != 0, "device does not support cooperative launches");
     TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    for (bool mixed : {false, true})
-      TT_HIP(hipFuncSetAttribute(kernel_ptr(mixed), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 d.lds_max - 1024));
+    for (int v = 0; v < 3; ++v)
+      TT_HIP(hipFuncSetAttribute(kernel_ptr(v == 2, v == 1),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
     di[dev] = d;
     ready[dev] = true;
   }
@@ -642,8 +845,17 @@ int grid_cap() {
 
 struct Plan {
   int G = 0, spw = 0, m = 0, ldv = 0;
+  bool mf = false;
   size_t lds_bytes = 0;
 };
+
+bool mfma_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("TTNT_KRYLOV_MFMA");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
 
 size_t lds_bytes_for(const KrylovShape& sh, int m, int ldv, bool mixed) {
   const size_t dbl = (size_t)kAsDoubles + kBsDoubles + (size_t)sh.n * sh.RR * sh.r1 + ldv +
@@ -679,6 +891,11 @@ Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mix
   }
   p.m = m;
   p.lds_bytes = lds_bytes_for(sh, m, p.ldv, mixed);
+  // the matrix-core kernel: one slice per workgroup,
+  // n RR <= 128, n r0 <= 80, and the fragment-ordered v fits in Bs
+  const int64_t k1 = (int64_t)sh.n * sh.r0, m1 = (int64_t)sh.n * sh.RR;
+  p.mf = !mixed && mfma_enabled() && p.spw == 1 && m1 <= 16 * 4 * kMfmaMT &&
+         k1 <= 4 * kMfmaKS && cdiv(k1, (int64_t)4) * cdiv((int64_t)sh.r1, (int64_t)16) * 64 <= kBFull;
   return p;
 }
 
@@ -779,8 +996,8 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
 
   int per_cu = 0;
-  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_ptr(mixed), kThreads,
-                                                      p.lds_bytes));
+  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_ptr(mixed, p.mf),
+                                                      kThreads, p.lds_bytes));
   TT_REQUIRE((int64_t)per_cu * di.cus >= p.G, "Krylov solve: grid exceeds co-resident capacity");
 
   if (mixed) {
@@ -795,7 +1012,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   void* args[] = {&a};
   {
     std::lock_guard<std::mutex> lock(g_dev_mu);
-    TT_HIP(hipLaunchCooperativeKernel(kernel_ptr(mixed), dim3(p.G), dim3(kThreads), args,
+    TT_HIP(hipLaunchCooperativeKernel(kernel_ptr(mixed, p.mf), dim3(p.G), dim3(kThreads), args,
                                       p.lds_bytes, s));
   }
   if (pe) g_probe->end(s);

@@ -249,6 +249,10 @@ __global__ void trunc_rank_kernel(const double* __restrict__ S, int n, double to
   if (discard) *discard += disc;
 }
 
+// Odd leading dimension for LDS-resident matrices: lanes walking different
+// rows (or columns) at the same index hit different banks.
+__host__ __device__ __forceinline__ int odd_ld(int m) { return m | 1; }
+
 // Dense LU with partial pivoting and solve, in place (A N x N, b length N).
 __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, int N, int ldag,
                                                       double* __restrict__ bg, int use_lds) {
@@ -259,10 +263,10 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
   double* b = bg;
   int lda = ldag;
   if (use_lds) {
+    lda = odd_ld(N);
     A = sm;
-    b = sm + N * N;
-    lda = N;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[e] = Ag[(int64_t)(e / N) * ldag + e % N];
+    b = sm + N * lda;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) A[(e / N) * lda + e % N] = Ag[(int64_t)(e / N) * ldag + e % N];
     for (int e = threadIdx.x; e < N; e += blockDim.x) b[e] = bg[e];
     __syncthreads();
   }
@@ -339,7 +343,6 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
 // ---------------------------------------------------------------------------
 constexpr int WS = 256;
 
-__host__ __device__ __forceinline__ int odd_ld(int m) { return m | 1; }
 
 // Rows [j + 1, m) split into four contiguous segments, one per wavefront.
 __device__ __forceinline__ void row_segment(int j, int m, int w, int& r0, int& r1) {
@@ -711,6 +714,8 @@ int lds_limit() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_lds_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_solve_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
     lim[d] = v;
   }
   return lim[d];
@@ -761,9 +766,10 @@ void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,
 void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   if (N <= 0 || batch <= 0) return;
   ++g_launches;
-  const bool lds = (int64_t)N * N + N <= kLdsDoubles;
-  lu_solve_kernel<<<batch, WG, lds ? (size_t)((int64_t)N * N + N) * 8 : 0, s>>>(A, N, lda, b,
-                                                                                 lds ? 1 : 0);
+  // One workgroup per system; the matrix lives in LDS when it fits (N <= 141).
+  const size_t need = ((size_t)N * odd_ld(N) + N) * 8;
+  const bool lds = need <= (size_t)lds_limit();
+  lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 

@@ -26,6 +26,7 @@ struct Solver {
   double k_host = 1.0;
   double stall = 0.5;          // stop sweeping when the residual falls by less than this
   double cap_eta = 1e-2;       // local residual reduction while the rank cap binds
+  int min_sweeps = 2;          // sweeps before the stagnation test may stop
   bool cap_bound = false;      // the rank cap bound during the previous sweep
   std::vector<char> Hdiag;
   int64_t last_launches = 0;

@@ -259,6 +259,12 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   lso.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
   lso.eta = 0.0;
   TT_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 or 1");
+  TT_REQUIRE(o->min_sweeps >= 0 && o->cap_eta >= 0.0 && o->cap_eta < 1.0 && o->stall >= 0.0 &&
+                 o->stall <= 1.0,
+             "bad sweep-stopping options");
+  if (o->min_sweeps > 0) min_sweeps = o->min_sweeps;
+  if (o->cap_eta > 0.0) cap_eta = o->cap_eta;
+  if (o->stall > 0.0) stall = o->stall;
   lso.mixed = o->precision == 1;
   // identity operator (explicit mode right-hand side)
   Id.d = d;
@@ -581,7 +587,7 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
     if (max_res < tol) break;
     cap_bound = st.cap_hit;
     // stagnation: the rank cap bound and the residual no longer falls
-    if (st.cap_hit && sweeps >= 2 && max_res > stall * prev_res) break;
+    if (st.cap_hit && sweeps >= min_sweeps && max_res > stall * prev_res) break;
     prev_res = max_res;
   }
   // compress the solution and update k

@@ -79,7 +79,9 @@ class TTSolverOpts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int32), ("rhs_mode", ctypes.c_int32),
                 ("rhs_rmax", ctypes.c_int32), ("local_tol", ctypes.c_double),
                 ("gmres_restart", ctypes.c_int32), ("gmres_max_iter", ctypes.c_int32),
-                ("direct_max", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("direct_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("min_sweeps", ctypes.c_int32), ("cap_eta", ctypes.c_double),
+                ("stall", ctypes.c_double)]
 
 
 class TTProbeStats(ctypes.Structure):
@@ -333,13 +335,15 @@ class Solver:
                  k0: float = 1.0, tol: float = 1e-8, rmax: int = 32, kick: int = 4,
                  max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  local_tol: float = 0.0, gmres_restart: int = 80, gmres_max_iter: int = 2000,
-                 direct_max: int = 256, precision: int = 0):
+                 direct_max: int = 256, precision: int = 0, min_sweeps: int = 0,
+                 cap_eta: float = 0.0, stall: float = 0.0):
         self._hold = (H, SF, F_core0, cF, psi0)
         prob = TTProblem(H.desc(), SF.desc(), ctypes.c_void_p(F_core0.data_ptr()), cF.desc(),
                          psi0.desc(), float(k0))
         opts = TTSolverOpts(float(tol), int(rmax), int(kick), int(max_sweeps), int(rhs_mode),
                             int(rhs_rmax), float(local_tol), int(gmres_restart),
-                            int(gmres_max_iter), int(direct_max), int(precision))
+                            int(gmres_max_iter), int(direct_max), int(precision),
+                            int(min_sweeps), float(cap_eta), float(stall))
         h = ctypes.c_void_p()
         _check(lib().tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h

@@ -65,7 +65,8 @@ def joint_rhs_operator(S, F, tol: float = 1e-13):
 class KeffSolver:
     def __init__(self, wl, rmax: Optional[int] = None, tol: Optional[float] = None,
                  kick: int = 4, max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
-                 direct_max: int = 256, gmres_restart: int = 80, ops=None, precision: int = 0):
+                 direct_max: int = 256, gmres_restart: int = 80, ops=None, precision: int = 0,
+                 min_sweeps: int = 0, cap_eta: float = 0.0, stall: float = 0.0):
         import torch
         self.wl = wl
         self.rmax = wl.rmax if rmax is None else rmax
@@ -84,7 +85,8 @@ class KeffSolver:
                                     tol=self.tol, rmax=self.rmax, kick=kick,
                                     max_sweeps=max_sweeps, rhs_mode=rhs_mode,
                                     rhs_rmax=rhs_rmax, direct_max=direct_max,
-                                    gmres_restart=gmres_restart, precision=precision)
+                                    gmres_restart=gmres_restart, precision=precision,
+                                    min_sweeps=min_sweeps, cap_eta=cap_eta, stall=stall)
         self.history: List[StepRecord] = []
 
     @property
@@ -119,7 +121,7 @@ class KeffSolver:
 
 def step_batched(solvers: List["KeffSolver"], streams) -> List[StepRecord]:
     """One power step of each KeffSolver, run concurrently on `streams`
-    (torch.cuda.Stream objects; one host thread per stream in the library)."""
+    (torch.cuda.Stream objects) by the library's single-threaded scheduler."""
     t0 = time.perf_counter()
     infos = native.power_step_batched([s.native for s in solvers], streams)
     dt = time.perf_counter() - t0

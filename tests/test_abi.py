@@ -106,6 +106,12 @@ def test_solver_rejects_bad_options():
     assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
     opts = native.TTSolverOpts(1e-8, 4, 4, 10, 7, 0, 0.0, 40, 100, 64)   # bad rhs_mode
     assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
+    for field, bad in [("cap_eta", 1.5), ("stall", 2.0), ("min_sweeps", -1)]:
+        opts = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64)
+        setattr(opts, field, bad)
+        assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts),
+                                    ctypes.byref(h)) == native.TT_E_ARG, field
+        assert b"sweep-stopping" in lib.tt_last_error()
     prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, -1.0)  # k0 <= 0
     opts = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64)
     assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG

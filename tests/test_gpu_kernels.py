@@ -141,6 +141,9 @@ def _local_system(rng, ra, RL, n, RR, rc, shift=8.0):
 @pytest.mark.parametrize("method,ra,RL,n,RR,rc", [
     (1, 3, 2, 2, 3, 4),      # dense LU
     (1, 8, 5, 2, 4, 8),
+    (1, 7, 3, 2, 3, 10),     # N = 140: largest LDS-resident LU
+    (1, 9, 3, 2, 3, 8),      # N = 144: global-memory LU
+    (1, 5, 3, 2, 4, 25),     # N = 250
     (2, 6, 4, 2, 5, 7),      # GMRES
     (2, 16, 6, 2, 6, 16),
     (0, 4, 3, 24, 3, 5),     # automatic (angle-like core)

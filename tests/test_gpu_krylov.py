@@ -43,6 +43,8 @@ CASES = [
     (9, 5, 3, 4, 11, 12, False),     # general 3-point mode, many restarts
     (16, 6, 2, 6, 16, 88, True),     # longest restart
     (1, 1, 2, 1, 1, 80, True),       # two unknowns
+    (36, 6, 2, 8, 36, 80, True),     # rank 32 + enrichment: matrix-core first product, 2592 unknowns
+    (12, 4, 2, 60, 10, 30, True),    # 120 rows of Q_a: every wavefront's second m-tile
 ]
 
 
