@@ -141,59 +141,88 @@ __device__ __forceinline__ void row_dots(const E* __restrict__ pr, const E* __re
 }
 
 // FP64 form of the same sums for the matrix-core kernel: lane `part` reads the
-// units part, part + P, ... of the row, a unit being W consecutive doubles
-// (W = 2: 16-byte loads, K even and pr 16-byte aligned).  The stream is read
-// in blocks of 32 / W units per lane, double-buffered: the loads of block
-// b + 1 are in flight while block b is multiplied.
-template <int NI, int W>
+// units part, part + P, ... of the row (P = PC when PC > 0), a unit being W
+// consecutive doubles (W = 2: 16-byte loads, K even and pr 16-byte aligned).
+// The stream is read in blocks of 32 / W units per lane, double-buffered: the
+// loads of block b + 1 are issued before block b is multiplied.  The blocks
+// that are whole for every lane run in a loop whose trip count is the same
+// in every lane and whose loads are unconditional, so the number of loads in
+// flight is known on every path and each wait covers only the block in use;
+// the rest of the row is one more block, its loads clamped to the row and
+// its products past the end skipped.
+template <int NI, int W, int PC>
 __device__ __forceinline__ void row_dots_pipe(const double* __restrict__ pr,
                                               const double* __restrict__ t, int K, int part,
-                                              int P, double* acc) {
-  constexpr int U = 32 / W;
+                                              int Pr, double* acc) {
+  constexpr int U = 32 / W, G = 4;
+  // a compile-time lane count turns a block's addresses into immediate
+  // offsets from one base
+  const int P = PC > 0 ? PC : Pr;
   typedef double V __attribute__((ext_vector_type(W)));
   const V* pu = reinterpret_cast<const V*>(pr);
   const int KU = K / W, S = P * U, span = P * (U - 1);
+  const int nfull = KU - P - span >= 0 ? (KU - P - span) / S + 1 : 0;
   V pa[U], pb[U];
   auto load = [&](V* buf, int k0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) buf[u] = pu[k0 + P * u];
   };
+  // the LDS operands of G units are read together before their products
   auto mac = [&](const V* buf, int k0) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = (k0 + P * u) * W;
+    for (int g = 0; g < U; g += G) {
+      V tv[NI][G];
 #pragma unroll
-      for (int q = 0; q < NI; ++q) {
-        const V tv = *reinterpret_cast<const V*>(t + q * K + k);
+      for (int u = 0; u < G; ++u)
 #pragma unroll
-        for (int h = 0; h < W; ++h) acc[q] = fma(tv[h], buf[u][h], acc[q]);
-      }
+        for (int q = 0; q < NI; ++q)
+          tv[q][u] = *reinterpret_cast<const V*>(t + q * K + (k0 + P * (g + u)) * W);
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int q = 0; q < NI; ++q)
+#pragma unroll
+          for (int h = 0; h < W; ++h) acc[q] = fma(tv[q][u][h], buf[g + u][h], acc[q]);
     }
   };
   int kb = part;
-  if (kb + span < KU) {
+  if (nfull > 0) {
     load(pa, kb);
-    while (true) {
-      int kn = kb + S;
-      bool more = kn + span < KU;
-      if (more) load(pb, kn);
+    int b = 0;
+    while (b + 2 < nfull) {
+      load(pb, kb + S);
       mac(pa, kb);
-      kb = kn;
-      if (!more) break;
-      kn = kb + S;
-      more = kn + span < KU;
-      if (more) load(pa, kn);
-      mac(pb, kb);
-      kb = kn;
-      if (!more) break;
+      load(pa, kb + 2 * S);
+      mac(pb, kb + S);
+      kb += 2 * S;
+      b += 2;
+    }
+    if (b + 1 < nfull) {
+      load(pb, kb + S);
+      mac(pa, kb);
+      mac(pb, kb + S);
+      kb += 2 * S;
+    } else {
+      mac(pa, kb);
+      kb += S;
     }
   }
-  for (; kb < KU; kb += P) {
-    const V pv = pu[kb];
+  // the partial block left to this lane
+  if (kb < KU) {
 #pragma unroll
-    for (int q = 0; q < NI; ++q)
+    for (int u = 0; u < U; ++u) pa[u] = pu[min(kb + P * u, KU - 1)];
 #pragma unroll
-      for (int h = 0; h < W; ++h) acc[q] = fma(t[q * K + kb * W + h], pv[h], acc[q]);
+    for (int u = 0; u < U; ++u) {
+      const int ku = kb + P * u;
+      if (ku < KU) {
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+          const V tv = *reinterpret_cast<const V*>(t + q * K + ku * W);
+#pragma unroll
+          for (int h = 0; h < W; ++h) acc[q] = fma(tv[h], pa[u][h], acc[q]);
+        }
+      }
+    }
   }
 }
 
@@ -358,13 +387,11 @@ __device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const 
       if (tid < rows * P && cr < a.r1) {
         const double* pr = a.phiR + (int64_t)cr * K;
         const double* t2 = Ts + (int64_t)i0 * K;
-        if (w2) {
-          if (ni == 2) row_dots_pipe<2, 2>(pr, t2, K, part, P, acc);
-          else row_dots_pipe<1, 2>(pr, t2, K, part, P, acc);
-        } else {
-          if (ni == 2) row_dots_pipe<2, 1>(pr, t2, K, part, P, acc);
-          else row_dots_pipe<1, 1>(pr, t2, K, part, P, acc);
-        }
+        // ranks 33-36 and 29-32 (P = 7, 8) take the pipelined stream
+        if (w2 && ni == 2 && P == 7) row_dots_pipe<2, 2, 7>(pr, t2, K, part, P, acc);
+        else if (w2 && ni == 2 && P == 8) row_dots_pipe<2, 2, 8>(pr, t2, K, part, P, acc);
+        else if (ni == 2) row_dots<2, double>(pr, t2, K, part, P, acc);
+        else row_dots<1, double>(pr, t2, K, part, P, acc);
       }
       red[tid] = acc[0];
       red[kThreads + tid] = acc[1];
