@@ -481,7 +481,8 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const double* v, 
   QFrag qf;
   load_qfrag(a.Q + (int64_t)c.a0 * M1 * K1, M1, K1, qf);
   {
-    constexpr int kB = 8;
+    // all of a thread's coherent loads in flight together (up to 16)
+    constexpr int kB = 16;
     const int total = ksu * NT * 64;
     __syncthreads();
     for (int e0 = tid; e0 < total; e0 += kB * kThreads) {
@@ -536,7 +537,7 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const double* v, 
 // A d = r in FP32 to inner_tol (or to the global target) and x += d in FP64.
 template <typename T, bool MF>
 __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
-  extern __shared__ double lds[];
+  extern __shared__ __attribute__((aligned(16))) double lds[];   // 16-byte reads of Ts
   __shared__ double red[4];
   __shared__ double bcast[4];
   constexpr bool kMixed = sizeof(T) < sizeof(double);
