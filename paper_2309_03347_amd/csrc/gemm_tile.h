@@ -12,12 +12,17 @@ constexpr int kTileM = 64, kTileN = 64, kTileK = 16;
 // over k in [kb, ke), computed by 256 threads.  Each thread owns a 4x4 block
 // (rows tr*4+i, columns tc+16*j, so C stores are coalesced).  With raw the
 // unscaled partial sum is stored.  Row-major operands; op = transpose if flag.
+// The next 16-wide K chunk is loaded into registers while the current one is
+// multiplied out of LDS, so a chunk's load latency overlaps the previous
+// chunk's products.
 template <bool TA, bool TB>
 __device__ __forceinline__ void gemm_tile(int tm, int tn, int M, int N, int kb, int ke,
                                           double alpha, const double* __restrict__ A, int lda,
                                           const double* __restrict__ B, int ldb, double beta,
                                           double* __restrict__ C, int ldc, bool raw,
                                           double (*As)[kTileM + 1], double (*Bs)[kTileN + 1]) {
+  constexpr int NL = (kTileM * kTileK) / 256;      // loads per thread and operand
+  static_assert((kTileK * kTileN) / 256 == NL, "square tile");
   const int m0 = tm * kTileM, n0 = tn * kTileN;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   double acc[4][4];
@@ -25,28 +30,43 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int M, int N, int kb, 
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += kTileK) {
+  double ra[NL], rb[NL];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < (kTileM * kTileK) / 256; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int e = tid + t * 256;
       int mm, kk;
       if (!TA) { mm = e / kTileK; kk = e % kTileK; } else { kk = e / kTileM; mm = e % kTileM; }
       const int gm = m0 + mm, gk = k0 + kk;
       double v = 0.0;
       if (gm < M && gk < ke) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[kk][mm] = v;
+      ra[t] = v;
     }
 #pragma unroll
-    for (int t = 0; t < (kTileK * kTileN) / 256; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int e = tid + t * 256;
       int kk, nn;
       if (!TB) { kk = e / kTileN; nn = e % kTileN; } else { nn = e / kTileK; kk = e % kTileK; }
       const int gk = k0 + kk, gn = n0 + nn;
       double v = 0.0;
       if (gk < ke && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[kk][nn] = v;
+      rb[t] = v;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+      const int e = tid + t * 256;
+      if (!TA) As[e % kTileK][e / kTileK] = ra[t]; else As[e / kTileM][e % kTileM] = ra[t];
+      if (!TB) Bs[e / kTileN][e % kTileN] = rb[t]; else Bs[e % kTileK][e / kTileK] = rb[t];
+    }
+  };
+  load(kb);
+  for (int k0 = kb; k0 < ke; k0 += kTileK) {
     __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + kTileK < ke) load(k0 + kTileK);
 #pragma unroll
     for (int kk = 0; kk < kTileK; ++kk) {
       double a[4], b[4];
@@ -59,7 +79,6 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int M, int N, int kb, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
