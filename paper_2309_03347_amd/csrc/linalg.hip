@@ -512,6 +512,25 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __hiloint2double(h2, l2);
 }
 
+// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton
+// steps each (x finite, nonzero; x > 0 for the square root), accurate to the
+// last bits for the rotation parameters of the Jacobi sweeps.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 // Sum over aligned groups of Lp lanes.  Every exchange pairs lanes by an
 // involution (xor 1, xor 2, mirror within 8, mirror within 16, then xor 16
 // and xor 32), so all lanes of a group hold the bit-identical sum.
@@ -534,7 +553,7 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
                                                      double* __restrict__ S,
                                                      double* __restrict__ V, int ldv) {
   extern __shared__ double sm[];
-  __shared__ int s_rot;
+  __shared__ int s_rot, s_big;
   __shared__ double s_fro;
   const int ld = odd_ld(m), ldn = odd_ld(n), tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* A = sm;                               // ld x n
@@ -576,7 +595,10 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
   while (Lp > 1 && npair * Lp > WS) Lp >>= 1;
   const int g = tid / Lp, l = tid % Lp;
   for (int sweep = 0; sweep < 60 && np > 1; ++sweep) {
-    if (tid == 0) s_rot = 0;
+    if (tid == 0) {
+      s_rot = 0;
+      s_big = 0;
+    }
     __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
       int p = 0, q = 0;
@@ -601,10 +623,21 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
       a = group_sum(a, Lp);
       b = group_sum(b, Lp);
       gg = group_sum(gg, Lp);
-      if (valid && gg != 0.0 && fabs(gg) > tol * sqrt(a * b) && a > sfmin && b > sfmin) {
-        const double zeta = (b - a) / (2.0 * gg);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+      // |g| > tol sqrt(a b) tested as g (g / a) > tol^2 b (no overflow: g^2 <= a b)
+      const double ga = valid && a > sfmin ? gg * rcp_nr(a) : 0.0;
+      if (valid && gg != 0.0 && ga * gg > tol * tol * b && a > sfmin && b > sfmin) {
+        // a rotation above 1e-10 (relative) keeps the sweeps going
+        if (l == 0 && ga * gg > 1e-20 * b) s_big = 1;
+        const double zeta = (b - a) * 0.5 * rcp_nr(gg);
+        const double az = fabs(zeta);
+        double t;
+        if (az > 1e150) {
+          t = 0.5 * rcp_nr(zeta);
+        } else {
+          const double z2 = fma(zeta, zeta, 1.0);
+          t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + z2 * rsq_nr(z2));
+        }
+        const double c = rsq_nr(fma(t, t, 1.0)), sn = c * t;
         double* wp = Wm + (int64_t)p * ldn;
         double* wq = Wm + (int64_t)q * ldn;
         for (int e = l; e < n; e += Lp) {
@@ -619,9 +652,11 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
       }
       __syncthreads();
     }
-    const int rot = s_rot;
+    const int rot = s_rot, big = s_big;
     __syncthreads();
-    if (rot == 0) break;
+    // Jacobi sweeps converge quadratically: after a sweep whose rotations were
+    // all below 1e-10, the next one's would be below the 1e-15 threshold
+    if (rot == 0 || big == 0) break;
   }
   // singular values and their descending order
   for (int c = w; c < n; c += 4) {
