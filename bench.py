@@ -33,9 +33,9 @@ PEAK_FP64_TFLOPS = 78.6
 # valid only while the kernel's sources are unchanged.
 MEASURED_TRAFFIC = {
     ("krylov", "inner_box_n32_G4_S4"): dict(
-        bytes_per_launch=19.19e6,
-        sources={"paper_2309_03347_amd/csrc/krylov.hip": "885ba82cda4d33b4",
-                 "paper_2309_03347_amd/csrc/gemm_tile.h": "a9a928d54389a255"}),
+        bytes_per_launch=19.62e6,
+        sources={"paper_2309_03347_amd/csrc/krylov.hip": "db433afc46b226b1",
+                 "paper_2309_03347_amd/csrc/gemm_tile.h": "8641b1e5a94501dd"}),
 }
 
 
