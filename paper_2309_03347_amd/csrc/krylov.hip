@@ -140,25 +140,25 @@ __device__ __forceinline__ void row_dots(const E* __restrict__ pr, const E* __re
   }
 }
 
-// FP64 form of the same sums for the matrix-core kernel: lane `part` reads the
-// units part, part + P, ... of the row (P = PC when PC > 0), a unit being W
-// consecutive doubles (W = 2: 16-byte loads, K even and pr 16-byte aligned).
-// The stream is read in blocks of 32 / W units per lane, double-buffered: the
-// loads of block b + 1 are issued before block b is multiplied.  The blocks
+// The matrix-core kernel's form of the same sums: lane `part` reads the units
+// part, part + P, ... of the row (P = PC when PC > 0), a unit being W
+// consecutive elements (16-byte loads when W sizeof(E) = 16: K a multiple of
+// W and pr 16-byte aligned).  The stream is read in blocks of 256 bytes per
+// lane (16 units of 16 bytes), double-buffered: the loads of block b + 1 are
+// issued before block b is multiplied.  The blocks
 // that are whole for every lane run in a loop whose trip count is the same
 // in every lane and whose loads are unconditional, so the number of loads in
 // flight is known on every path and each wait covers only the block in use;
 // the rest of the row is one more block, its loads clamped to the row and
 // its products past the end skipped.
-template <int NI, int W, int PC>
-__device__ __forceinline__ void row_dots_pipe(const double* __restrict__ pr,
-                                              const double* __restrict__ t, int K, int part,
-                                              int Pr, double* acc) {
-  constexpr int U = 32 / W, G = 4;
+template <int NI, int W, int PC, typename E>
+__device__ __forceinline__ void row_dots_pipe(const E* __restrict__ pr, const E* __restrict__ t,
+                                              int K, int part, int Pr, E* acc) {
+  constexpr int U = 256 / (W * (int)sizeof(E)), G = 4;
   // a compile-time lane count turns a block's addresses into immediate
   // offsets from one base
   const int P = PC > 0 ? PC : Pr;
-  typedef double V __attribute__((ext_vector_type(W)));
+  typedef E V __attribute__((ext_vector_type(W)));
   const V* pu = reinterpret_cast<const V*>(pr);
   const int KU = K / W, S = P * U, span = P * (U - 1);
   const int nfull = KU - P - span >= 0 ? (KU - P - span) / S + 1 : 0;
@@ -286,32 +286,56 @@ __device__ __forceinline__ void gemm_tile_ldsb(int tm, int tn, int M, int N, int
   }
 }
 
-// MFMA form of the first product when a workgroup owns one slice (FP64).
+// Matrix-core form of the first product when a workgroup owns one slice.
 // The slice's folded operator Q_a (n RR <= 128 rows, n r0 <= 80 columns) is
-// the A operand of the FP64 16x16x4 matrix instruction, loaded straight into
-// the fragment registers; the right operand v ((n r0) x r1, r1 <= 64) is
-// staged in LDS in fragment order, one 64-double fragment per (k-step,
-// n-tile), so every fragment read is 64 consecutive doubles.  Lane l of a
-// wavefront holds A[l % 16][l / 16], B[l / 16][l % 16] and
-// D[l / 16 + 4 r][l % 16], r < 4.  Wavefront w owns the m-tiles w and w + 4.
+// the A operand of the 16x16x4 matrix instruction (FP64, or FP32 in the
+// refinement cycles), loaded straight into the fragment registers; the right
+// operand v ((n r0) x r1, r1 <= 64) is staged in LDS in fragment order, one
+// 64-element fragment per (k-step, n-tile), so every fragment read is 64
+// consecutive elements.  Lane l of a wavefront holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its four results are D[l / 16 + 4 r][l % 16] in FP64
+// and D[4 (l / 16) + r][l % 16] in FP32 (both checked on the device).
+// Wavefront w owns the m-tiles w and w + 4.
 constexpr int kMfmaKS = 20;      // k-steps of 4: n r0 <= 80
 constexpr int kMfmaMT = 2;       // m-tiles of 16 per wavefront
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
+template <typename E>
+struct MfmaOps;
+template <>
+struct MfmaOps<double> {
+  typedef dbl4 Acc;
+  static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <>
+struct MfmaOps<float> {
+  typedef flt4 Acc;
+  static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+template <typename E>
 struct QFrag {
-  double q[kMfmaMT][kMfmaKS];
+  E q[kMfmaMT][kMfmaKS];
 };
 
 // Q_a (M1 x K1, row-major) into the wavefront's A fragments.
-__device__ __forceinline__ void load_qfrag(const double* __restrict__ Qa, int M1, int K1,
-                                           QFrag& f) {
+template <typename E>
+__device__ __forceinline__ void load_qfrag(const E* __restrict__ Qa, int M1, int K1,
+                                           QFrag<E>& f) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
   for (int mt = 0; mt < kMfmaMT; ++mt)
 #pragma unroll
     for (int ks = 0; ks < kMfmaKS; ++ks) {
       const int mm = 16 * (w + 4 * mt) + (l & 15), kk = 4 * ks + (l >> 4);
-      f.q[mt][ks] = (mm < M1 && kk < K1) ? Qa[(int64_t)mm * K1 + kk] : 0.0;
+      f.q[mt][ks] = (mm < M1 && kk < K1) ? Qa[(int64_t)mm * K1 + kk] : E(0);
     }
 }
 
@@ -370,35 +394,37 @@ __device__ __forceinline__ void stage3(const SArgs& a, const Ctx& c, const E* ph
   __syncthreads();
 }
 
-// The matrix-core kernel's form (FP64): every thread streams part of one row
+// The matrix-core kernel's form: every thread streams part of one row
 // of PhiR, P = 256 / r1 lanes per row (any P), and the P partial sums of a
 // row are added in a fixed order through LDS (red: 4 x 256 doubles).
-__device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const double* Ts,
-                                            double* ys) {
+template <typename E>
+__device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const E* phiRe,
+                                            const E* Ts, E* ys) {
+  constexpr int W = 16 / (int)sizeof(E);
   const int tid = c.tid, K = c.K3;
   const int P = max(1, min(64, kThreads / a.r1)), rows = kThreads / P;
-  const bool w2 = (K % 2 == 0) && ((reinterpret_cast<uintptr_t>(a.phiR) & 15) == 0);
-  double* red = c.As;
+  const bool w2 = (K % W == 0) && ((reinterpret_cast<uintptr_t>(phiRe) & 15) == 0);
+  E* red = reinterpret_cast<E*>(c.As);
   for (int c0 = 0; c0 < a.r1; c0 += rows) {
     const int cr = c0 + tid / P, part = tid % P;
     for (int i0 = 0; i0 < a.n; i0 += 2) {
       const int ni = min(2, a.n - i0);
-      double acc[2] = {0.0, 0.0};
+      E acc[2] = {E(0), E(0)};
       if (tid < rows * P && cr < a.r1) {
-        const double* pr = a.phiR + (int64_t)cr * K;
-        const double* t2 = Ts + (int64_t)i0 * K;
+        const E* pr = phiRe + (int64_t)cr * K;
+        const E* t2 = Ts + (int64_t)i0 * K;
         // ranks 33-36 and 29-32 (P = 7, 8) take the pipelined stream
-        if (w2 && ni == 2 && P == 7) row_dots_pipe<2, 2, 7>(pr, t2, K, part, P, acc);
-        else if (w2 && ni == 2 && P == 8) row_dots_pipe<2, 2, 8>(pr, t2, K, part, P, acc);
-        else if (ni == 2) row_dots<2, double>(pr, t2, K, part, P, acc);
-        else row_dots<1, double>(pr, t2, K, part, P, acc);
+        if (w2 && ni == 2 && P == 7) row_dots_pipe<2, W, 7, E>(pr, t2, K, part, P, acc);
+        else if (w2 && ni == 2 && P == 8) row_dots_pipe<2, W, 8, E>(pr, t2, K, part, P, acc);
+        else if (ni == 2) row_dots<2, E>(pr, t2, K, part, P, acc);
+        else row_dots<1, E>(pr, t2, K, part, P, acc);
       }
       red[tid] = acc[0];
       red[kThreads + tid] = acc[1];
       __syncthreads();
       if (tid < rows && c0 + tid < a.r1) {
         for (int q = 0; q < ni; ++q) {
-          double sum = 0.0;
+          E sum = E(0);
           for (int p = 0; p < P; ++p) sum += red[q * kThreads + tid * P + p];
           ys[(i0 + q) * a.r1 + c0 + tid] = sum;
         }
@@ -468,33 +494,36 @@ __device__ void apply_slices(const SArgs& a, const Ctx& c, const E* Qe, const E*
   }
 }
 
-// The same product for one slice per workgroup (FP64) on the matrix cores:
+// The same product for one slice per workgroup on the matrix cores, in E:
 // the A fragments of Q_a are loaded first (all in flight together, L2
 // resident after the first use), v is staged into Bs in fragment order while
 // they arrive, the first product goes into Ts and the second is stage3_pipe.
-__device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const double* v, double alpha,
-                                 double* out) {
+template <typename E>
+__device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const E* Qe, const E* phiRe,
+                                 const E* v, E alpha, E* out) {
+  typedef MfmaOps<E> Ops;
+  typedef typename Ops::Acc Acc;
   const int tid = c.tid, l = c.lane, w = tid >> 6;
   const int K1 = c.nr0, M1 = c.nRR, NT = cdiv(a.r1, 16), ksu = cdiv(K1, 4);
-  double* Bs = c.Bs;
-  double* Ts = c.Ts;
-  QFrag qf;
-  load_qfrag(a.Q + (int64_t)c.a0 * M1 * K1, M1, K1, qf);
+  E* Bs = reinterpret_cast<E*>(c.Bs);
+  E* Ts = reinterpret_cast<E*>(c.Ts);
+  QFrag<E> qf;
+  load_qfrag<E>(Qe + (int64_t)c.a0 * M1 * K1, M1, K1, qf);
   {
     // all of a thread's coherent loads in flight together (up to 16)
     constexpr int kB = 16;
     const int total = ksu * NT * 64;
     __syncthreads();
     for (int e0 = tid; e0 < total; e0 += kB * kThreads) {
-      double tmp[kB];
+      E tmp[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         const int e = e0 + u * kThreads;
-        double val = 0.0;
+        E val = E(0);
         if (e < total) {
           const int frag = e >> 6, ln = e & 63, ks = frag / NT, nt = frag - ks * NT;
           const int kk = 4 * ks + (ln >> 4), j = 16 * nt + (ln & 15);
-          if (kk < K1 && j < a.r1) val = ld_coherent(v + (int64_t)kk * a.r1 + j);
+          if (kk < K1 && j < a.r1) val = ld_coh<E>(v + (int64_t)kk * a.r1 + j);
         }
         tmp[u] = val;
       }
@@ -508,27 +537,27 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const double* v, 
   }
   const bool second = 16 * (w + 4) < M1;     // the wavefront's second m-tile holds rows
   for (int nt = 0; nt < NT; ++nt) {
-    dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    Acc acc0 = {E(0), E(0), E(0), E(0)}, acc1 = acc0;
 #pragma unroll
     for (int ks = 0; ks < kMfmaKS; ++ks) {
       if (ks < ksu) {
-        const double bv = Bs[(ks * NT + nt) * 64 + l];
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qf.q[0][ks], bv, acc0, 0, 0, 0);
-        if (second) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qf.q[1][ks], bv, acc1, 0, 0, 0);
+        const E bv = Bs[(ks * NT + nt) * 64 + l];
+        acc0 = Ops::mma(qf.q[0][ks], bv, acc0);
+        if (second) acc1 = Ops::mma(qf.q[1][ks], bv, acc1);
       }
     }
     const int j = 16 * nt + (l & 15);
     if (j < a.r1) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m0 = 16 * w + (l >> 4) + 4 * r, m1 = m0 + 64;
+        const int m0 = 16 * w + Ops::row(l, r), m1 = m0 + 64;
         if (m0 < M1) Ts[m0 * a.r1 + j] = alpha * acc0[r];
         if (second && m1 < M1) Ts[m1 * a.r1 + j] = alpha * acc1[r];
       }
     }
   }
   __syncthreads();
-  stage3_pipe(a, c, Ts, out);
+  stage3_pipe<E>(a, c, phiRe, Ts, out);
 }
 
 // The solve.  T is the working precision of the Krylov iterations; restart
@@ -600,7 +629,6 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       __syncthreads();
     }
   }
-  static_assert(!(MF && kMixed), "the matrix-core path is FP64");
 
   // Partial dots of w with V_0..V_j over the chunk (gs lanes per vector, FP64 sums).
   auto dots = [&](int j, const T* w, double* out) {
@@ -681,7 +709,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     // r = f - A x in FP64 (x and the FP64 operator); r is rounded into Vl_0
     // and W (unnormalised).  ||r||^2 and ||f||^2.
     if constexpr (MF)
-      apply_slice_mfma(a, c, a.x, 1.0, c.Yd);
+      apply_slice_mfma<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd);
     else
       apply_slices<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd, fullB64);
     double rr = 0.0, ff = 0.0;
@@ -729,8 +757,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     while (true) {
       T* w = Vl + (int64_t)(j + 1) * ldv;
       if constexpr (MF)
-        apply_slice_mfma(a, c, reinterpret_cast<const double*>(W), 1.0 / nu,
-                         reinterpret_cast<double*>(w));
+        apply_slice_mfma<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w);
       else
         apply_slices<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w, fullBw);
       // normalise V_j (its norm is known now), first-pass dots
@@ -830,7 +857,9 @@ constexpr int kMaxDev = 64;
 std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
 
 const void* kernel_ptr(bool mixed, bool mf) {
-  if (mixed) return reinterpret_cast<const void*>(gmres_slices_kernel<float, false>);
+  if (mixed)
+    return mf ? reinterpret_cast<const void*>(gmres_slices_kernel<float, true>)
+              : reinterpret_cast<const void*>(gmres_slices_kernel<float, false>);
   return mf ? reinterpret_cast<const void*>(gmres_slices_kernel<double, true>)
             : reinterpret_cast<const void*>(gmres_slices_kernel<double, false>);
 }
@@ -851,8 +880,8 @@ DevInfo dev_info() {
     TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     TT_REQUIRE(coop != 0, "device does not support cooperative launches");
     TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    for (int v = 0; v < 3; ++v)
-      TT_HIP(hipFuncSetAttribute(kernel_ptr(v == 2, v == 1),
+    for (int v = 0; v < 4; ++v)
+      TT_HIP(hipFuncSetAttribute(kernel_ptr(v >= 2, (v & 1) != 0),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
     di[dev] = d;
     ready[dev] = true;
@@ -922,7 +951,7 @@ Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mix
   // the matrix-core kernel: one slice per workgroup,
   // n RR <= 128, n r0 <= 80, and the fragment-ordered v fits in Bs
   const int64_t k1 = (int64_t)sh.n * sh.r0, m1 = (int64_t)sh.n * sh.RR;
-  p.mf = !mixed && mfma_enabled() && p.spw == 1 && m1 <= 16 * 4 * kMfmaMT &&
+  p.mf = mfma_enabled() && p.spw == 1 && m1 <= 16 * 4 * kMfmaMT &&
          k1 <= 4 * kMfmaKS && cdiv(k1, (int64_t)4) * cdiv((int64_t)sh.r1, (int64_t)16) * 64 <= kBFull;
   return p;
 }

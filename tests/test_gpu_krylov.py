@@ -44,6 +44,7 @@ CASES = [
     (16, 6, 2, 6, 16, 88, True),     # longest restart
     (1, 1, 2, 1, 1, 80, True),       # two unknowns
     (36, 6, 2, 8, 36, 80, True),     # rank 32 + enrichment: matrix-core first product, 2592 unknowns
+    (32, 4, 2, 6, 32, 80, True),     # rank 32: eight lanes per PhiR row
     (12, 4, 2, 60, 10, 30, True),    # 120 rows of Q_a: every wavefront's second m-tile
     (41, 4, 2, 5, 9, 30, True),      # n r0 = 82 > 80: the vector-FMA first product
 ]
