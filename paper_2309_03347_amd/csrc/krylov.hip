@@ -63,14 +63,16 @@ struct SArgs {
   double* info;         // [iterations, converged, |g_k| / ||f||]
 };
 
-// Grid barrier for a cooperative launch: each wave writes its stores back to
-// the agent coherence point, one thread per workgroup counts in and waits for
-// the epoch.  Readers of data from other workgroups use ld_coherent.
+// Grid barrier for a cooperative launch: the workgroup barrier makes every
+// wave's stores complete in the workgroup's L2, then one thread writes the L2
+// back to the agent coherence point (release at agent scope, which orders the
+// whole workgroup's earlier stores), counts in and waits for the epoch.
+// Readers of data from other workgroups use ld_coherent.
 __device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target) {
   target += gridDim.x;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
       __builtin_amdgcn_s_sleep(1);
