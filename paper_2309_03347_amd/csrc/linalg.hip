@@ -343,15 +343,6 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
 // ---------------------------------------------------------------------------
 constexpr int WS = 256;
 
-
-// Rows [j + 1, m) split into four contiguous segments, one per wavefront.
-__device__ __forceinline__ void row_segment(int j, int m, int w, int& r0, int& r1) {
-  const int len = m - j - 1;
-  const int seg = len > 0 ? (len + 3) / 4 : 0;
-  r0 = j + 1 + w * seg;
-  r1 = min(m, r0 + seg);
-}
-
 // sum_{r in [r0, r1)} x[r] y[r] + init, LDS operands loaded eight at a time.
 __device__ __forceinline__ double seg_dot(const double* x, const double* y, int r0, int r1,
                                           double init) {
@@ -388,23 +379,40 @@ __device__ __forceinline__ void seg_axpy(double alpha, const double* x, double* 
   for (; r < r1; ++r) y[r] = fma(alpha, x[r], y[r]);
 }
 
+// Rows of the four wavefronts: wavefront w owns the fixed block
+// [w B, (w + 1) B), B = ceil(m / 4), of every column for the whole
+// factorization, so a wavefront only ever reads rows it wrote itself and the
+// workgroup barriers are needed only where partial sums cross wavefronts.
+// Step j works on the rows below j: [max(j + 1, w B), min(m, (w + 1) B)).
+__device__ __forceinline__ void row_block(int j, int m, int w, int& r0, int& r1) {
+  const int B = (m + 3) / 4;
+  r0 = max(j + 1, w * B);
+  r1 = min(m, (w + 1) * B);
+}
+__device__ __forceinline__ int row_owner(int r, int m) { return r / ((m + 3) / 4); }
+
 // Householder QR of the column-major m x n matrix A (leading dimension ld):
 // the upper triangle receives R, the part below the diagonal the reflector
 // vectors (unit leading entry implicit), tau[j] the factors of
-// H_j = I - tau_j v_j v_j^T.  pw is LDS scratch of 4 * (n + 1) doubles.
+// H_j = I - tau_j v_j v_j^T.  pw is LDS scratch of 8 (n + 1) + 4 doubles: the
+// norm partials, and the column-dot partials in two halves used on
+// alternate steps.  Two workgroup barriers per column.
 __device__ void hh_qr(double* A, int m, int n, int ld, double* tau, double* pw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int k = min(m, n);
+  double* pn = pw + 8 * (n + 1);
   for (int j = 0; j < k; ++j) {
     double* aj = A + (int64_t)j * ld;
+    double* pd = pw + (j & 1) * 4 * (n + 1);
+    const bool diag = row_owner(j, m) == w;    // this wavefront holds row j
     int r0, r1;
-    row_segment(j, m, w, r0, r1);
+    row_block(j, m, w, r0, r1);
     double s = 0.0;
     for (int r = r0 + lane; r < r1; r += 64) s = fma(aj[r], aj[r], s);
     s = wave_sum(s);
-    if (lane == 0) pw[w] = s;
+    if (lane == 0) pn[w] = s;
     __syncthreads();
-    const double nrm2 = (pw[0] + pw[1]) + (pw[2] + pw[3]);
+    const double nrm2 = (pn[0] + pn[1]) + (pn[2] + pn[3]);
     const double alpha = aj[j];
     double t = 0.0, beta = alpha, inv = 0.0;
     if (nrm2 > 0.0) {
@@ -414,63 +422,62 @@ __device__ void hh_qr(double* A, int m, int n, int ld, double* tau, double* pw) 
       inv = 1.0 / (alpha - beta);
     }
     for (int r = r0 + lane; r < r1; r += 64) aj[r] *= inv;
+    // partial w_c over this wavefront's rows (the implicit 1 of v_j meets row j)
+    for (int c = j + 1 + lane; c < n; c += 64) {
+      const double* ac = A + (int64_t)c * ld;
+      pd[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, diag ? ac[j] : 0.0);
+    }
     __syncthreads();
-    if (tid == 0) {
+    if (t != 0.0) {
+      for (int c = j + 1 + lane; c < n; c += 64) {
+        double* ac = A + (int64_t)c * ld;
+        const double wc = t * ((pd[c] + pd[(n + 1) + c]) +
+                               (pd[2 * (n + 1) + c] + pd[3 * (n + 1) + c]));
+        seg_axpy(-wc, aj, ac, r0, r1);
+        if (diag) ac[j] -= wc;
+      }
+    }
+    if (diag && lane == 0) {
       aj[j] = beta;
       tau[j] = t;
     }
-    if (t != 0.0) {
-      // partial w_c over this wavefront's rows
-      for (int c = j + 1 + lane; c < n; c += 64) {
-        const double* ac = A + (int64_t)c * ld;
-        pw[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, w == 0 ? ac[j] : 0.0);
-      }
-      __syncthreads();
-      for (int c = j + 1 + lane; c < n; c += 64) {
-        double* ac = A + (int64_t)c * ld;
-        const double wc = t * ((pw[c] + pw[(n + 1) + c]) +
-                               (pw[2 * (n + 1) + c] + pw[3 * (n + 1) + c]));
-        seg_axpy(-wc, aj, ac, r0, r1);
-        if (w == 0) ac[j] -= wc;
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
-// Overwrites the reflector storage of hh_qr with the first k = min(m, n)
-// columns of Q = H_0 ... H_{k-1} [I_k; 0].  R must have been copied out.
+// Q = H_0 ... H_{k-1} [I; 0] in place of the reflectors (columns 0..k-1),
+// backwards, one workgroup barrier per column.  Rows above the diagonal of
+// column c are only written by the later steps j < c (as -w_c); they are
+// never read before, so they need no zeroing.  pw as in hh_qr.
 __device__ void hh_form_q(double* A, int m, int n, int ld, const double* tau, double* pw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int k = min(m, n);
   for (int j = k - 1; j >= 0; --j) {
     double* aj = A + (int64_t)j * ld;
+    double* pd = pw + (j & 1) * 4 * (n + 1);
     const double t = tau[j];
+    const bool diag = row_owner(j, m) == w;
     int r0, r1;
-    row_segment(j, m, w, r0, r1);
-    if (t != 0.0) {
-      for (int c = j + 1 + lane; c < k; c += 64) {
-        const double* ac = A + (int64_t)c * ld;
-        pw[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, w == 0 ? ac[j] : 0.0);
-      }
+    row_block(j, m, w, r0, r1);
+    // row j of the columns c > j is still zero here: only rows below j count
+    for (int c = j + 1 + lane; c < k; c += 64) {
+      const double* ac = A + (int64_t)c * ld;
+      pd[w * (n + 1) + c] = seg_dot(aj, ac, r0, r1, 0.0);
     }
     __syncthreads();
-    if (t != 0.0) {
-      for (int c = j + 1 + lane; c < k; c += 64) {
-        double* ac = A + (int64_t)c * ld;
-        const double wc = t * ((pw[c] + pw[(n + 1) + c]) +
-                               (pw[2 * (n + 1) + c] + pw[3 * (n + 1) + c]));
-        seg_axpy(-wc, aj, ac, r0, r1);
-        if (w == 0) ac[j] -= wc;
-      }
+    for (int c = j + 1 + lane; c < k; c += 64) {
+      double* ac = A + (int64_t)c * ld;
+      const double wc = t != 0.0 ? t * ((pd[c] + pd[(n + 1) + c]) +
+                                        (pd[2 * (n + 1) + c] + pd[3 * (n + 1) + c]))
+                                 : 0.0;
+      if (wc != 0.0) seg_axpy(-wc, aj, ac, r0, r1);
+      if (diag) ac[j] = -wc;
     }
-    __syncthreads();
     // column j of Q: (1 - t) e_j - t v_j
     for (int r = r0 + lane; r < r1; r += 64) aj[r] *= -t;
-    if (tid == 0) aj[j] = 1.0 - t;
-    for (int r = tid; r < j; r += WS) aj[r] = 0.0;
-    __syncthreads();
+    if (diag && lane == 0) aj[j] = 1.0 - t;
   }
+  __syncthreads();
 }
 
 // QR with diag(R) >= 0: Q (m x k), R (k x n), k = min(m, n); A row-major.
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
   double* tau = Wm + (int64_t)ldn * n;          // n
   double* sig = tau + n;                        // n
   double* rk = sig + n;                         // n
-  double* pw = rk + n;                          // 4 (n + 1)
+  double* pw = rk + n;                          // 8 (n + 1) + 4
   for (int e = tid; e < m * n; e += WS) {
     const int i = e / n, c = e % n;
     A[(int64_t)c * ld + i] = Gg[(int64_t)i * ldg + c];
@@ -724,11 +731,11 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
 }
 
 size_t qr_lds_doubles(int m, int n) {
-  return (size_t)odd_ld(m) * n + 2 * (size_t)std::min(m, n) + 4 * ((size_t)n + 1) + 8;
+  return (size_t)odd_ld(m) * n + 2 * (size_t)std::min(m, n) + 8 * ((size_t)n + 1) + 12;
 }
 size_t svd_lds_doubles(int m, int n) {
   return (size_t)odd_ld(m) * n + 2 * (size_t)odd_ld(n) * n + 3 * (size_t)n +
-         4 * ((size_t)n + 1) + 8;
+         8 * ((size_t)n + 1) + 12;
 }
 
 // Largest dynamic LDS allocation of one workgroup on the current device
