@@ -61,9 +61,12 @@ struct HostBuf {
   double* d;
 };
 // In-place rounding as a task (suspends once per truncated core); writes the
-// relative discarded norm to *rel_err (host) if rel_err != nullptr.
+// relative discarded norm to *rel_err (host) if rel_err != nullptr.  With
+// left_orth the caller guarantees cores 0..d-2 are already left-orthonormal
+// (for example after a left-to-right alternating sweep), and the QR sweep is
+// skipped.
 Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws,
-               SyncSlot& slot, HostBuf hb);
+               SyncSlot& slot, HostBuf hb, bool left_orth = false);
 // Blocking form of round_tt_co (synchronizes the stream).
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws);
 size_t round_ws_bytes(const TTv& x);

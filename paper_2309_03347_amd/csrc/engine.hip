@@ -146,7 +146,7 @@ void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump
 }
 
 Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws,
-               SyncSlot& slot, HostBuf hb) {
+               SyncSlot& slot, HostBuf hb, bool left_orth) {
   const int d = x.d;
   const int64_t mc = max_core(x);
   const int md = max_dim(x);
@@ -172,7 +172,7 @@ Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bum
     co_return;
   }
   // left-to-right Householder QR sweep
-  for (int k = 0; k < d - 1; ++k) {
+  for (int k = 0; k < d - 1 && !left_orth; ++k) {
     const int rows = x.r[k] * x.n[k], cols = x.r[k + 1];
     const int q = std::min(rows, cols);
     copy(s, x.core(k), W, (int64_t)rows * cols);

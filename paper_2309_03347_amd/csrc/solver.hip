@@ -593,7 +593,8 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
   // compress the solution and update k
   double trunc = 0.0;
   w.used = 0;
-  co_await round_tt_co(s, X, tol, rmax, &trunc, w, slot, hb);
+  // the left-to-right sweep left cores 0..d-2 orthonormal (QR of each split)
+  co_await round_tt_co(s, X, tol, rmax, &trunc, w, slot, hb, true);
   w.used = 0;
   dot_tt(s, cF, X, scal + NUM, w);
   k_update(s, scal + KVAL, scal + NUM, scal + DEN, scal + KINFO);
