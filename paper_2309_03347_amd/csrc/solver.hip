@@ -557,7 +557,9 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
   for (int sw = 0; sw < max_sweeps; ++sw) {
     st.cap_hit = false;
     w.used = 0;
-    orth_right(s, X, w);
+    // psi (hence X at the first sweep) is right-orthonormal in cores 1..d-1:
+    // it is orthogonalized at creation and left so by every step's rounding
+    if (sw > 0) orth_right(s, X, w);
     w.used = 0;
     orth_right(s, Z, w);
     for (int k = d - 1; k >= 1; --k) {
