@@ -72,7 +72,7 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-probe", action="store_true")
-    p.add_argument("--streams", type=int, default=8, help="streams of the batched workload")
+    p.add_argument("--streams", type=int, default=4, help="streams of the batched workload")
     p.add_argument("--build-workers", type=int, default=1,
                    help="host processes building the batched workload's operators")
     p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
