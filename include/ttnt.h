@@ -237,14 +237,18 @@ tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);
  * tt_power_step_batched - one power step of each of `count` independent
  * solvers (for example a parameter study of many small problems; each
  * instance is the iteration of eq. TT_k_eff_fixed_points on its own data).
- * The steps run concurrently: min(nstreams, count) host threads take the
- * solvers from a shared list, largest estimated cost first, and thread t
- * issues its work on streams[t].  Persistent local solves of a thread use at
- * most (compute units / threads) workgroups, so that the concurrent ones can
- * all be resident.  infos[i] receives solver i's step information.  Every
- * solver must appear once.  Returns TT_OK, TT_E_NOCONV if some step hit its
- * sweep limit, or the first other error of any instance (the remaining
- * instances still run).  Each stream is synchronized before return.
+ * The steps run concurrently from the calling thread: up to nstreams steps
+ * are in flight, one per stream, taken from the list largest estimated cost
+ * first; each step runs until it needs a device value on the host, and the
+ * thread resumes whichever step's stream event has completed.  Persistent
+ * local solves of a step use at most (compute units / min(nstreams, count))
+ * workgroups, so that the concurrent ones can all be resident.  Four streams
+ * match HIP's default of four hardware queues per process; more add no
+ * overlap.  infos[i]
+ * receives solver i's step information.  Every solver must appear once.
+ * Returns TT_OK, TT_E_NOCONV if some step hit its sweep limit, or the first
+ * other error of any instance (the remaining instances still run).  Each
+ * stream is synchronized before return.
  */
 tt_status tt_power_step_batched(tt_solver** solvers, int32_t count, tt_step_info* infos,
                                 const tt_stream* streams, int32_t nstreams);
