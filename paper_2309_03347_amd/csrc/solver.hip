@@ -294,19 +294,25 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   }
   Rop = rhs_mode == 0 ? SF.R : Id.R;
   // mode-diagonal cores of H (the transport operator does not couple groups
-  // or directions): their local systems split into independent blocks
+  // or directions): their local systems split into independent blocks.  A
+  // core counts as diagonal when its off-diagonal entries are at rounding
+  // level (below 1e-13 of its largest entry), as compressed operator cores
+  // are; the block solve then drops them.
   Hdiag.assign(d, false);
   for (int k = 0; k < d; ++k) {
     if (n[k] <= 2) continue;
     std::vector<double> h(H.size(k));
     TT_HIP(hipMemcpy(h.data(), H.core(k), h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double amax = 0.0;
+    for (double v : h) amax = std::max(amax, std::fabs(v));
+    const double cut = 1e-13 * amax;
     bool diag = true;
     for (int b = 0; b < H.R[k] && diag; ++b)
       for (int i = 0; i < n[k] && diag; ++i)
         for (int j = 0; j < n[k] && diag; ++j)
           if (i != j)
             for (int c = 0; c < H.R[k + 1]; ++c)
-              if (h[(((int64_t)b * n[k] + i) * n[k] + j) * H.R[k + 1] + c] != 0.0) {
+              if (std::fabs(h[(((int64_t)b * n[k] + i) * n[k] + j) * H.R[k + 1] + c]) > cut) {
                 diag = false;
                 break;
               }
