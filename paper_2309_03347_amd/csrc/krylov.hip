@@ -10,7 +10,8 @@
 // but nothing another workgroup computes:
 //   T[(i, beta'), d] = sum_{b, j} Q_a[(i, beta'), (b, j)] v[b, j, d]    (T in LDS)
 //   y[a, i, c]       = sum_{beta', d} T[(i, beta'), d] PhiR[c, beta', d]
-// so the operator application runs without grid barriers.  The workgroup's
+// so the operator application runs without grid barriers (the first product
+// on the matrix cores when a workgroup owns one slice).  The workgroup's
 // chunk of the Krylov basis stays in LDS for the whole solve; one Arnoldi
 // step (classical Gram-Schmidt, two passes) needs three grid barriers: after
 // the first-pass dots, after the second-pass dots, and after the new direction
