@@ -126,10 +126,14 @@ tt_status tt_dot(const tt_vec* a, const tt_vec* b, double* result, void* ws, siz
  * Shapes: PhiL [ra][RL][ra], A_k [RL][m][n][RR] with m == n, PhiR [rc][RR][rc],
  * f and x [ra][n][rc] (all device, row-major).  x holds the initial guess
  * on input and the solution on output.  method: 0 automatic (dense LU when
- * ra*n*rc <= direct_max, else restarted GMRES), 1 dense LU with partial
- * pivoting, 2 GMRES (one persistent cooperative kernel per solve, restart
- * length capped at 88), 4 GMRES with one launch per stage of each Arnoldi
- * step (same arithmetic, for comparison).  info (host) receives iterations and the final relative
+ * ra*n*rc <= direct_max, else restarted GMRES), 1 dense solve with partial
+ * pivoting (register Gauss-Jordan up to 192 unknowns, LU above), 2 GMRES (one
+ * persistent cooperative kernel per solve, restart length capped at 88), 3
+ * mode-diagonal block solve: only the entries A_k[b, i, i, b'] are used and
+ * the system splits into n dense (ra rc) x (ra rc) systems, solved as in
+ * method 1 (for cores whose operator is diagonal in the mode index, such as
+ * the angle core), 4 GMRES with one launch per stage of each Arnoldi step
+ * (same arithmetic, for comparison).  info (host) receives iterations and the final relative
  * residual ||A x - f|| / ||f||.  Returns TT_E_NOCONV if GMRES stops at
  * max_iter above tol (x still written).  Synchronizes `stream`.
  */
@@ -142,7 +146,8 @@ typedef struct {
 } tt_local;
 
 typedef struct {
-  int32_t method;       /* 0 auto, 1 LU, 2 GMRES (persistent), 4 GMRES (per-stage launches) */
+  int32_t method;       /* 0 auto, 1 dense, 2 GMRES (persistent), 3 mode-diagonal blocks,
+                           4 GMRES (per-stage launches) */
   double tol;           /* relative residual target for GMRES */
   int32_t max_iter;     /* total GMRES iterations */
   int32_t restart;      /* Krylov dimension per cycle */

@@ -212,8 +212,7 @@ tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* op
                "dimensions must be >= 1");
     TT_REQUIRE(sys->m == sys->n, "local operator must be square (m == n)");
     LocalSolveOpts so = solve_opts_from(opts);
-    TT_REQUIRE(so.method == 0 || so.method == 1 || so.method == 2 || so.method == 4,
-               "method must be 0, 1, 2 or 4");
+    TT_REQUIRE(so.method >= 0 && so.method <= 4, "method must be 0, 1, 2, 3 or 4");
     if (ws_bytes < tt_local_solve_workspace(sys, opts))
       throw CapacityError{"workspace smaller than tt_local_solve_workspace"};
     hipStream_t s = (hipStream_t)stream;
@@ -224,6 +223,7 @@ tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* op
     permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
     LocalOp op = local_op_from(sys);
     op.Ap = Ap;
+    op.diag = so.method == 3;
     LocalSolveResult r = local_solve(s, op, sys->f, x, so, w, true);
     if (info) {
       info->iterations = r.iterations;

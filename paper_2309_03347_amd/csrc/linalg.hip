@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <utility>
 
 #include "kernels.h"
 
@@ -538,6 +539,169 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return fma(y, e, y);
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident Gauss-Jordan solve for systems up to a few hundred
+// unknowns (the n blocks of a mode-diagonal core, small dense local systems).
+// ---------------------------------------------------------------------------
+
+// Pivot candidates are compared as (|x| bits, key): for non-negative doubles
+// the IEEE bit patterns order like the values, and key = 2 row + sign breaks
+// ties toward the lower row.  kGjNone (no candidate) loses to every row.
+constexpr int kGjNone = 0x7fffffff;
+
+__device__ __forceinline__ bool gj_better(uint64_t ob, int ok, uint64_t b, int k) {
+  return (ob > b) | ((ob == b) & (ok < k));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void gj_combine(uint64_t& bits, int& key) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)bits, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(bits >> 32), CTRL, 0xF, 0xF, false);
+  const int ok = __builtin_amdgcn_update_dpp(0, key, CTRL, 0xF, 0xF, false);
+  const uint64_t ob = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+  const bool t = gj_better(ob, ok, bits, key);
+  bits = t ? ob : bits;
+  key = t ? ok : key;
+}
+
+// Pivot search of one column by its sixteen owners, which form one DPP row
+// of a wavefront: the largest magnitude among rows not yet pivotal, the lowest
+// row on ties.  Writes the step's multipliers (zero for the pivot row), its
+// pivot row and its pivot value.
+template <int R>
+__device__ __forceinline__ void gj_pivot(const double (&col)[R], unsigned used, int ti, int j,
+                                         double* __restrict__ mult, int* __restrict__ sp,
+                                         double* __restrict__ pval, int* __restrict__ prow) {
+  uint64_t bits = 0;
+  int key = kGjNone;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const uint64_t xb = (uint64_t)__double_as_longlong(col[u]) & 0x7fffffffffffffffull;
+    const int xk = 2 * (ti + 16 * u) + (col[u] < 0.0 ? 1 : 0);
+    const bool t = !((used >> u) & 1u) & gj_better(xb, xk, bits, key);
+    bits = t ? xb : bits;
+    key = t ? xk : key;
+  }
+  gj_combine<0xB1>(bits, key);   // quad_perm [1,0,3,2]
+  gj_combine<0x4E>(bits, key);   // quad_perm [2,3,0,1]
+  gj_combine<0x141>(bits, key);  // row_half_mirror
+  gj_combine<0x140>(bits, key);  // row_mirror
+  const int p = key >> 1;
+  const double mag = __longlong_as_double((long long)bits);
+  const double piv = (key & 1) ? -mag : mag;
+  const double ip = piv != 0.0 ? rcp_nr(piv) : 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) mult[ti + 16 * u] = ti + 16 * u == p ? 0.0 : col[u] * ip;
+  if (ti == 0) {
+    *sp = p;
+    pval[j] = piv;
+    prow[j] = p;
+  }
+}
+
+// Gauss-Jordan elimination with partial pivoting of the augmented matrix
+// [A | b] held in registers, one workgroup of 16 TC threads per system.
+// Thread (tc, ti) = (tid / 16, tid % 16) holds rows i = ti + 16 u (u < R) and
+// columns c = tc + TC v (v < C) of [A | b], b being column N; N <= 16 R and
+// N + 1 <= TC C.  Rows are not exchanged: column j is eliminated from every
+// row but its pivot row p_j, so after N steps x_j = b'(p_j) / a(p_j, j).  A
+// zero pivot leaves x_j = 0, as the LU kernel does.
+//
+// One workgroup barrier per column: the column's sixteen owners (one DPP row)
+// find the pivot and publish it with the multipliers; every thread then takes
+// the pivot row's entries of its own columns from lane p % 16 of its own
+// sixteen-lane group (a cross-lane read, no LDS round trip) and applies the
+// rank-one update to its R x C block.  The multipliers and the pivot index are
+// double-buffered by step parity, so the next owners can write while slower
+// wavefronts still read.
+template <int R, int C, int TC>
+__global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restrict__ Ag, int N,
+                                                           int ldag, double* __restrict__ bg) {
+  __shared__ double mult[2][16 * R];
+  __shared__ double pval[16 * R], bfin[16 * R];
+  __shared__ int prow[16 * R];
+  __shared__ int sp[2];
+  const int tid = threadIdx.x, ti = tid & 15, tc = tid >> 4, gbase = tid & 48;
+  Ag += (int64_t)blockIdx.x * N * ldag;
+  bg += (int64_t)blockIdx.x * N;
+  double a[R][C];
+  unsigned used = 0;  // bit u: row ti + 16 u is a pivot row already, or padding
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = ti + 16 * u;
+    if (i >= N) used |= 1u << u;
+#pragma unroll
+    for (int v = 0; v < C; ++v) {
+      const int c = tc + TC * v;
+      a[u][v] = i < N ? (c < N ? Ag[(int64_t)i * ldag + c] : (c == N ? bg[i] : 0.0)) : 0.0;
+    }
+  }
+  // Column blocks v0 = 0 .. C-1 are expanded at compile time, so the pivot
+  // column's registers a[.][v0] have fixed indices; the TC columns of a block
+  // run as a loop.
+  auto block = [&](auto v0_c) {
+    constexpr int v0 = decltype(v0_c)::value;
+    for (int jc = 0; jc < TC; ++jc) {
+      const int j = TC * v0 + jc;
+      if (j >= N) return;
+      const int par = j & 1;
+      if (tc == jc) {
+        double col[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) col[u] = a[u][v0];
+        gj_pivot<R>(col, used, ti, j, mult[par], &sp[par], pval, prow);
+      }
+      __syncthreads();
+      const int p = __builtin_amdgcn_readfirstlane(sp[par]);
+      if (ti == (p & 15)) used |= 1u << (p >> 4);
+      double l[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) l[u] = mult[par][ti + 16 * u];
+      // the pivot row's entries of this thread's columns sit with lane p % 16
+      // of its group; one uniform branch per row block keeps register indices
+      // fixed
+      double rw[C] = {};
+      const int src = gbase | (p & 15), up = p >> 4;
+      [&]<int... Us>(std::integer_sequence<int, Us...>) {
+        (
+            [&] {
+              if (up == Us) {
+#pragma unroll
+                for (int v = 0; v < C; ++v) rw[v] = __shfl(a[Us][v], src, 64);
+              }
+            }(),
+            ...);
+      }(std::make_integer_sequence<int, R>{});
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < C; ++v) a[u][v] = fma(-l[u], rw[v], a[u][v]);
+      if (tc == jc) {
+        // the eliminated column is exactly zero outside the pivot row
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          if (ti + 16 * u != p) a[u][v0] = 0.0;
+      }
+    }
+  };
+  [&]<int... Vs>(std::integer_sequence<int, Vs...>) {
+    (block(std::integral_constant<int, Vs>{}), ...);
+  }(std::make_integer_sequence<int, C>{});
+  const int vb = N / TC, tb = N % TC;
+  if (tc == tb) {
+#pragma unroll
+    for (int v = 0; v < C; ++v)
+      if (v == vb)
+#pragma unroll
+        for (int u = 0; u < R; ++u) bfin[ti + 16 * u] = a[u][v];
+  }
+  __syncthreads();
+  for (int j = tid; j < N; j += 16 * TC) {
+    const double d = pval[j];
+    bg[j] = d != 0.0 ? bfin[prow[j]] / d : 0.0;
+  }
+}
+
 // Sum over aligned groups of Lp lanes.  Every exchange pairs lanes by an
 // involution (xor 1, xor 2, mirror within 8, mirror within 16, then xor 16
 // and xor 32), so all lanes of a group hold the bit-identical sum.
@@ -808,7 +972,22 @@ void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,
 void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   if (N <= 0 || batch <= 0) return;
   ++g_launches;
-  // One workgroup per system; the matrix lives in LDS when it fits (N <= 141).
+  // One workgroup per system.  Up to 192 unknowns the augmented matrix is
+  // held in registers (Gauss-Jordan); larger systems use the LU kernel, which
+  // works on an LDS copy only up to 141 unknowns.
+  if (N <= 64) {
+    gj_solve_kernel<4, 3, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
+  } else if (N <= 112) {
+    gj_solve_kernel<7, 4, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
+  } else if (N <= 144) {
+    gj_solve_kernel<9, 5, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
+  } else if (N <= 192) {
+    gj_solve_kernel<12, 7, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
+  }
+  if (N <= 192) {
+    TT_HIP(hipGetLastError());
+    return;
+  }
   const size_t need = ((size_t)N * odd_ld(N) + N) * 8;
   const bool lds = need <= (size_t)lds_limit();
   lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);

@@ -139,14 +139,21 @@ def _local_system(rng, ra, RL, n, RR, rc, shift=8.0):
 
 
 @pytest.mark.parametrize("method,ra,RL,n,RR,rc", [
-    (1, 3, 2, 2, 3, 4),      # dense LU
+    (1, 3, 2, 2, 3, 4),      # dense solve, N = 24 (register Gauss-Jordan)
+    (1, 4, 3, 2, 3, 8),      # N = 64: largest of the smallest register tile
+    (1, 5, 3, 2, 3, 13),     # N = 130
     (1, 8, 5, 2, 4, 8),
-    (1, 7, 3, 2, 3, 10),     # N = 140: largest LDS-resident LU
-    (1, 9, 3, 2, 3, 8),      # N = 144: global-memory LU
+    (1, 7, 3, 2, 3, 10),     # N = 140
+    (1, 9, 3, 2, 3, 8),      # N = 144: largest of its register tile
+    (1, 6, 3, 2, 3, 16),     # N = 192: largest register solve
+    (1, 7, 3, 2, 3, 14),     # N = 196: LU in global memory
     (1, 5, 3, 2, 4, 25),     # N = 250
     (2, 6, 4, 2, 5, 7),      # GMRES
     (2, 16, 6, 2, 6, 16),
-    (0, 4, 3, 24, 3, 5),     # automatic (angle-like core)
+    (0, 4, 3, 24, 3, 5),     # automatic (angle-like core): 24 blocks of 20
+    (3, 4, 3, 3, 3, 36),     # blocks of 144, as at the angle core of the 32^3 case
+    (3, 6, 3, 3, 3, 32),     # blocks of 192
+    (3, 5, 3, 3, 3, 40),     # blocks of 200: LU in global memory
 ])
 def test_local_solve_matches_dense(cuda, method, ra, RL, n, RR, rc):
     from paper_2309_03347_amd import native
