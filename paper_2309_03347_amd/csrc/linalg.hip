@@ -600,30 +600,38 @@ __device__ __forceinline__ void gj_pivot(const double (&col)[R], unsigned used, 
 }
 
 // Gauss-Jordan elimination with partial pivoting of the augmented matrix
-// [A | b] held in registers, one workgroup of 16 TC threads per system.
-// Thread (tc, ti) = (tid / 16, tid % 16) holds rows i = ti + 16 u (u < R) and
-// columns c = tc + TC v (v < C) of [A | b], b being column N; N <= 16 R and
-// N + 1 <= TC C.  Rows are not exchanged: column j is eliminated from every
-// row but its pivot row p_j, so after N steps x_j = b'(p_j) / a(p_j, j).  A
-// zero pivot leaves x_j = 0, as the LU kernel does.
+// [A | b], one workgroup of 16 TC threads per system.  Thread (tc, ti) =
+// (tid / 16, tid % 16) holds rows i = ti + 16 u (u < R) and columns
+// c = tc + TC v of [A | b], b being column N: the column blocks v < C in
+// registers and the next CE blocks in LDS (each thread's own slots, laid out
+// so that a wavefront's accesses are consecutive).  N <= 16 R and
+// N + 1 <= TC (C + CE).  Rows are not exchanged: column j is eliminated from
+// every row but its pivot row p_j, so after N steps x_j = b'(p_j) / a(p_j, j).
+// A zero pivot leaves x_j = 0, as the LU kernel does.
 //
 // One workgroup barrier per column: the column's sixteen owners (one DPP row)
 // find the pivot and publish it with the multipliers; every thread then takes
 // the pivot row's entries of its own columns from lane p % 16 of its own
 // sixteen-lane group (a cross-lane read, no LDS round trip) and applies the
-// rank-one update to its R x C block.  The multipliers and the pivot index are
+// rank-one update to its block.  The multipliers and the pivot index are
 // double-buffered by step parity, so the next owners can write while slower
 // wavefronts still read.
-template <int R, int C, int TC>
+template <int R, int C, int TC, int CE = 0>
 __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restrict__ Ag, int N,
                                                            int ldag, double* __restrict__ bg) {
+  constexpr int NT = 16 * TC;
   __shared__ double mult[2][16 * R];
   __shared__ double pval[16 * R], bfin[16 * R];
   __shared__ int prow[16 * R];
   __shared__ int sp[2];
+  extern __shared__ __attribute__((aligned(16))) double gj_lds[];  // CE R NT doubles
   const int tid = threadIdx.x, ti = tid & 15, tc = tid >> 4, gbase = tid & 48;
   Ag += (int64_t)blockIdx.x * N * ldag;
   bg += (int64_t)blockIdx.x * N;
+  auto ext = [&](int ve, int u) -> double& { return gj_lds[(ve * R + u) * NT + tid]; };
+  auto entry = [&](int i, int c) {
+    return i < N ? (c < N ? Ag[(int64_t)i * ldag + c] : (c == N ? bg[i] : 0.0)) : 0.0;
+  };
   double a[R][C];
   unsigned used = 0;  // bit u: row ti + 16 u is a pivot row already, or padding
 #pragma unroll
@@ -631,14 +639,13 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
     const int i = ti + 16 * u;
     if (i >= N) used |= 1u << u;
 #pragma unroll
-    for (int v = 0; v < C; ++v) {
-      const int c = tc + TC * v;
-      a[u][v] = i < N ? (c < N ? Ag[(int64_t)i * ldag + c] : (c == N ? bg[i] : 0.0)) : 0.0;
-    }
+    for (int v = 0; v < C; ++v) a[u][v] = entry(i, tc + TC * v);
+#pragma unroll
+    for (int ve = 0; ve < CE; ++ve) ext(ve, u) = entry(i, tc + TC * (C + ve));
   }
-  // Column blocks v0 = 0 .. C-1 are expanded at compile time, so the pivot
-  // column's registers a[.][v0] have fixed indices; the TC columns of a block
-  // run as a loop.
+  // Column blocks v0 = 0 .. C+CE-1 are expanded at compile time, so the pivot
+  // column's registers have fixed indices; the TC columns of a block run as a
+  // loop.
   auto block = [&](auto v0_c) {
     constexpr int v0 = decltype(v0_c)::value;
     for (int jc = 0; jc < TC; ++jc) {
@@ -648,7 +655,10 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
       if (tc == jc) {
         double col[R];
 #pragma unroll
-        for (int u = 0; u < R; ++u) col[u] = a[u][v0];
+        for (int u = 0; u < R; ++u) {
+          if constexpr (v0 < C) col[u] = a[u][v0];
+          else col[u] = ext(v0 - C, u);
+        }
         gj_pivot<R>(col, used, ti, j, mult[par], &sp[par], pval, prow);
       }
       __syncthreads();
@@ -660,7 +670,7 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
       // the pivot row's entries of this thread's columns sit with lane p % 16
       // of its group; one uniform branch per row block keeps register indices
       // fixed
-      double rw[C] = {};
+      double rw[C] = {}, rwe[CE > 0 ? CE : 1] = {};
       const int src = gbase | (p & 15), up = p >> 4;
       [&]<int... Us>(std::integer_sequence<int, Us...>) {
         (
@@ -668,25 +678,33 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
               if (up == Us) {
 #pragma unroll
                 for (int v = 0; v < C; ++v) rw[v] = __shfl(a[Us][v], src, 64);
+#pragma unroll
+                for (int ve = 0; ve < CE; ++ve) rwe[ve] = __shfl(ext(ve, Us), src, 64);
               }
             }(),
             ...);
       }(std::make_integer_sequence<int, R>{});
 #pragma unroll
-      for (int u = 0; u < R; ++u)
+      for (int u = 0; u < R; ++u) {
 #pragma unroll
         for (int v = 0; v < C; ++v) a[u][v] = fma(-l[u], rw[v], a[u][v]);
+#pragma unroll
+        for (int ve = 0; ve < CE; ++ve) ext(ve, u) = fma(-l[u], rwe[ve], ext(ve, u));
+      }
       if (tc == jc) {
         // the eliminated column is exactly zero outside the pivot row
 #pragma unroll
         for (int u = 0; u < R; ++u)
-          if (ti + 16 * u != p) a[u][v0] = 0.0;
+          if (ti + 16 * u != p) {
+            if constexpr (v0 < C) a[u][v0] = 0.0;
+            else ext(v0 - C, u) = 0.0;
+          }
       }
     }
   };
   [&]<int... Vs>(std::integer_sequence<int, Vs...>) {
     (block(std::integral_constant<int, Vs>{}), ...);
-  }(std::make_integer_sequence<int, C>{});
+  }(std::make_integer_sequence<int, C + CE>{});
   const int vb = N / TC, tb = N % TC;
   if (tc == tb) {
 #pragma unroll
@@ -694,13 +712,23 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
       if (v == vb)
 #pragma unroll
         for (int u = 0; u < R; ++u) bfin[ti + 16 * u] = a[u][v];
+#pragma unroll
+    for (int ve = 0; ve < CE; ++ve)
+      if (C + ve == vb)
+#pragma unroll
+        for (int u = 0; u < R; ++u) bfin[ti + 16 * u] = ext(ve, u);
   }
   __syncthreads();
-  for (int j = tid; j < N; j += 16 * TC) {
+  for (int j = tid; j < N; j += NT) {
     const double d = pval[j];
     bg[j] = d != 0.0 ? bfin[prow[j]] / d : 0.0;
   }
 }
+
+// The Gauss-Jordan instantiation with two of its eight column blocks in LDS
+// (systems of 193 to 240 unknowns) and its dynamic LDS bytes.
+constexpr int kGjExtR = 15, kGjExtC = 6, kGjExtTC = 32, kGjExtCE = 2;
+constexpr size_t kGjExtLds = (size_t)kGjExtCE * kGjExtR * 16 * kGjExtTC * sizeof(double);
 
 // Sum over aligned groups of Lp lanes.  Every exchange pairs lanes by an
 // involution (xor 1, xor 2, mirror within 8, mirror within 16, then xor 16
@@ -922,6 +950,9 @@ int lds_limit() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_solve_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    TT_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(gj_solve_kernel<kGjExtR, kGjExtC, kGjExtTC, kGjExtCE>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::min<size_t>(kGjExtLds, v)));
     lim[d] = v;
   }
   return lim[d];
@@ -972,9 +1003,9 @@ void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,
 void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   if (N <= 0 || batch <= 0) return;
   ++g_launches;
-  // One workgroup per system.  Up to 192 unknowns the augmented matrix is
-  // held in registers (Gauss-Jordan); larger systems use the LU kernel, which
-  // works on an LDS copy only up to 141 unknowns.
+  // One workgroup per system.  Gauss-Jordan up to 240 unknowns, with the
+  // augmented matrix in registers (up to 192) or in registers and LDS; larger
+  // systems use the LU kernel (in global memory beyond 141 unknowns).
   if (N <= 64) {
     gj_solve_kernel<4, 3, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
   } else if (N <= 112) {
@@ -983,14 +1014,14 @@ void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
     gj_solve_kernel<9, 5, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
   } else if (N <= 192) {
     gj_solve_kernel<12, 7, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
+  } else if (N <= 16 * kGjExtR && kGjExtLds <= (size_t)lds_limit()) {
+    gj_solve_kernel<kGjExtR, kGjExtC, kGjExtTC, kGjExtCE>
+        <<<batch, 16 * kGjExtTC, kGjExtLds, s>>>(A, N, lda, b);
+  } else {
+    const size_t need = ((size_t)N * odd_ld(N) + N) * 8;
+    const bool lds = need <= (size_t)lds_limit();
+    lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);
   }
-  if (N <= 192) {
-    TT_HIP(hipGetLastError());
-    return;
-  }
-  const size_t need = ((size_t)N * odd_ld(N) + N) * 8;
-  const bool lds = need <= (size_t)lds_limit();
-  lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 

@@ -145,9 +145,11 @@ def _local_system(rng, ra, RL, n, RR, rc, shift=8.0):
     (1, 8, 5, 2, 4, 8),
     (1, 7, 3, 2, 3, 10),     # N = 140
     (1, 9, 3, 2, 3, 8),      # N = 144: largest of its register tile
-    (1, 6, 3, 2, 3, 16),     # N = 192: largest register solve
-    (1, 7, 3, 2, 3, 14),     # N = 196: LU in global memory
-    (1, 5, 3, 2, 4, 25),     # N = 250
+    (1, 6, 3, 2, 3, 16),     # N = 192: largest all-register solve
+    (1, 7, 3, 2, 3, 14),     # N = 196: two column blocks in LDS
+    (1, 9, 3, 2, 3, 13),     # N = 234, a system of the 32^3 case
+    (1, 8, 3, 2, 3, 15),     # N = 240: largest Gauss-Jordan solve
+    (1, 5, 3, 2, 4, 25),     # N = 250: LU in global memory
     (2, 6, 4, 2, 5, 7),      # GMRES
     (2, 16, 6, 2, 6, 16),
     (0, 4, 3, 24, 3, 5),     # automatic (angle-like core): 24 blocks of 20
