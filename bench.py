@@ -108,7 +108,8 @@ def _cpu_baseline(wl, seconds: float):
 def _time_to_k(wl, rmax, rhs_mode, max_steps, rel=1e-5, precision=0):
     """Wall time from the first step of a fresh solver until k stays within
     `rel` of the converged k of the same iteration (the last k when
-    |dk| < tol_k, else the last k of the run, flagged unconverged)."""
+    |dk| < tol_k, else the last k of the run, flagged unconverged).  A time is
+    reported only when k then stayed within `rel` for at least five steps."""
     import torch
     from paper_2309_03347_amd.solver import KeffSolver
     s = KeffSolver(wl, rmax=rmax, rhs_mode=rhs_mode, precision=precision)
@@ -134,8 +135,10 @@ def _time_to_k(wl, rmax, rhs_mode, max_steps, rel=1e-5, precision=0):
     out = dict(rel=rel, k_ref=k_ref, converged=converged, steps=len(ks),
                tail_rel_spread=(max(tail) - min(tail)) / abs(k_ref))
     # A k that is still drifting by more than `rel` per step has no meaningful
-    # time-to-k: report null with the observed spread.
-    if hit is not None and (converged or out["tail_rel_spread"] <= rel):
+    # time-to-k (a single small |dk| can stop a run whose k still wanders):
+    # report null with the observed spread.
+    settled = hit is not None and len(ks) - hit >= 5
+    if settled and (converged or out["tail_rel_spread"] <= rel):
         out.update(seconds=times[hit], step=hit + 1)
     else:
         out.update(seconds=None, step=None)
