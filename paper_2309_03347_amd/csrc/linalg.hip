@@ -730,23 +730,26 @@ __global__ __launch_bounds__(16 * TC) void gj_solve_kernel(const double* __restr
 constexpr int kGjExtR = 15, kGjExtC = 6, kGjExtTC = 32, kGjExtCE = 2;
 constexpr size_t kGjExtLds = (size_t)kGjExtCE * kGjExtR * 16 * kGjExtTC * sizeof(double);
 
-// Sum over aligned groups of Lp lanes.  Every exchange pairs lanes by an
+// Sum over aligned groups of LP lanes.  Every exchange pairs lanes by an
 // involution (xor 1, xor 2, mirror within 8, mirror within 16, then xor 16
 // and xor 32), so all lanes of a group hold the bit-identical sum.
-__device__ __forceinline__ double group_sum(double v, int Lp) {
-  if (Lp >= 2) v += dpp_move<0xB1>(v);     // quad_perm [1, 0, 3, 2]
-  if (Lp >= 4) v += dpp_move<0x4E>(v);     // quad_perm [2, 3, 0, 1]
-  if (Lp >= 8) v += dpp_move<0x141>(v);    // row_half_mirror
-  if (Lp >= 16) v += dpp_move<0x140>(v);   // row_mirror
-  if (Lp >= 32) v += __shfl_xor(v, 16, 64);
-  if (Lp >= 64) v += __shfl_xor(v, 32, 64);
+template <int LP>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (LP >= 2) v += dpp_move<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+  if constexpr (LP >= 4) v += dpp_move<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+  if constexpr (LP >= 8) v += dpp_move<0x141>(v);    // row_half_mirror
+  if constexpr (LP >= 16) v += dpp_move<0x140>(v);   // row_mirror
+  if constexpr (LP >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (LP >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
 // Thin SVD G = U S V^T (m >= n), G row-major.  Householder QR G = Q R, then
 // one-sided Jacobi on R^T: R^T W = Y with orthogonal columns, so that
 // U = Q W and V = Y diag(1 / |Y_j|).  Singular values sorted descending;
-// each column of U has its largest-magnitude entry positive.
+// each column of U has its largest-magnitude entry positive.  LP lanes serve
+// one Jacobi pair (the largest power of two with LP (n + 1) / 2 <= 256).
+template <int LP>
 __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ Gg, int m, int n,
                                                      int ldg, double* __restrict__ U, int ldu,
                                                      double* __restrict__ S,
@@ -790,8 +793,7 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
   const double sfmin = s_fro * (2.3e-16 * 2.3e-16);
   const double tol = 1e-15;
   const int np = n + (n & 1), npair = np / 2;
-  int Lp = 64;
-  while (Lp > 1 && npair * Lp > WS) Lp >>= 1;
+  constexpr int Lp = LP;
   const int g = tid / Lp, l = tid % Lp;
   for (int sweep = 0; sweep < 60 && np > 1; ++sweep) {
     if (tid == 0) {
@@ -799,15 +801,21 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
       s_big = 0;
     }
     __syncthreads();
+    // Round-robin tournament: position 0 holds player 0 and position k > 0
+    // holds player 1 + (k - 1 + round) mod (np - 1).  This group plays
+    // positions g and np - 1 - g; both offsets advance by one per round.
+    int cp = g - 1, cq = np - 2 - g;
     for (int round = 0; round < np - 1; ++round) {
       int p = 0, q = 0;
       bool valid = false;
       if (g < npair) {
-        p = rr_player(g, round, np);
-        q = rr_player(np - 1 - g, round, np);
+        p = g == 0 ? 0 : 1 + cp;
+        q = 1 + cq;
         if (p > q) { const int tq = p; p = q; q = tq; }
         valid = q < n;
       }
+      cp = cp + 1 == np - 1 ? 0 : cp + 1;
+      cq = cq + 1 == np - 1 ? 0 : cq + 1;
       double a = 0.0, b = 0.0, gg = 0.0;
       double* yp = Y + (int64_t)p * ldn;
       double* yq = Y + (int64_t)q * ldn;
@@ -819,12 +827,14 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
           gg = fma(x, y, gg);
         }
       }
-      a = group_sum(a, Lp);
-      b = group_sum(b, Lp);
-      gg = group_sum(gg, Lp);
-      // |g| > tol sqrt(a b) tested as g (g / a) > tol^2 b (no overflow: g^2 <= a b)
-      const double ga = valid && a > sfmin ? gg * rcp_nr(a) : 0.0;
-      if (valid && gg != 0.0 && ga * gg > tol * tol * b && a > sfmin && b > sfmin) {
+      a = group_sum<LP>(a);
+      b = group_sum<LP>(b);
+      gg = group_sum<LP>(gg);
+      // |g| > tol sqrt(a b) tested as g (g / a) > tol^2 b (no overflow: g^2 <= a b);
+      // the conditions are combined without short-circuit branches
+      const bool ok = valid & (a > sfmin) & (b > sfmin) & (gg != 0.0);
+      const double ga = ok ? gg * rcp_nr(a) : 0.0;
+      if (ok & (ga * gg > tol * tol * b)) {
         // a rotation above 1e-10 (relative) keeps the sweeps going
         if (l == 0 && ga * gg > 1e-20 * b) s_big = 1;
         const double zeta = (b - a) * 0.5 * rcp_nr(gg);
@@ -946,8 +956,12 @@ int lds_limit() {
     v -= 1024;
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(qr_lds_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
-    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_lds_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    for (const void* k : {reinterpret_cast<const void*>(svd_lds_kernel<4>),
+                          reinterpret_cast<const void*>(svd_lds_kernel<8>),
+                          reinterpret_cast<const void*>(svd_lds_kernel<16>),
+                          reinterpret_cast<const void*>(svd_lds_kernel<32>),
+                          reinterpret_cast<const void*>(svd_lds_kernel<64>)})
+      TT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_solve_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(
@@ -982,8 +996,20 @@ void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, do
   if (m <= 0 || n <= 0) return;
   TT_REQUIRE(m >= n, "svd expects m >= n");
   ++g_launches;
-  if (svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
-    svd_lds_kernel<<<1, WS, svd_lds_doubles(m, n) * 8, s>>>(G, m, n, ldg, U, ldu, S, V, ldv);
+  // lanes per Jacobi pair: the largest power of two (at most 64) that lets
+  // all (n + 1) / 2 pairs of a round run at once in 256 threads
+  const int npair = (n + 1) / 2;
+  int lp = 64;
+  while (lp > 4 && npair * lp > WS) lp >>= 1;
+  if (npair * lp <= WS && svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
+    const size_t lds = svd_lds_doubles(m, n) * 8;
+    switch (lp) {
+      case 64: svd_lds_kernel<64><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
+      case 32: svd_lds_kernel<32><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
+      case 16: svd_lds_kernel<16><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
+      case 8: svd_lds_kernel<8><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
+      default: svd_lds_kernel<4><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
+    }
     TT_HIP(hipGetLastError());
     return;
   }
