@@ -344,6 +344,56 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
 // ---------------------------------------------------------------------------
 constexpr int WS = 256;
 
+// One DPP lane exchange of a double (two 32-bit moves).
+template <int Ctrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, Ctrl, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, Ctrl, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton
+// steps each (x finite, nonzero; x > 0 for the square root), accurate to the
+// last bits for the rotation parameters of the Jacobi sweeps.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
+// Sum over the 64 lanes of a wavefront, returned to every lane: four DPP
+// exchanges within each row of 16 lanes, two row broadcasts that gather the
+// row sums into the last row (row_mask picks the rows that add), and a read
+// of lane 63.  About a third of the latency of six cross-lane shuffles.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), Ctrl, RowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), Ctrl, RowMask, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_move<0xB1>(v);              // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);              // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);             // row_half_mirror
+  v += dpp_move<0x140>(v);             // row_mirror
+  v += dpp_bcast<0x142, 0xA>(v);       // row_bcast:15 into rows 1 and 3
+  v += dpp_bcast<0x143, 0xC>(v);       // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // sum_{r in [r0, r1)} x[r] y[r] + init, LDS operands loaded eight at a time.
 __device__ __forceinline__ double seg_dot(const double* x, const double* y, int r0, int r1,
                                           double init) {
@@ -390,7 +440,6 @@ __device__ __forceinline__ void row_block(int j, int m, int w, int& r0, int& r1)
   r0 = max(j + 1, w * B);
   r1 = min(m, (w + 1) * B);
 }
-__device__ __forceinline__ int row_owner(int r, int m) { return r / ((m + 3) / 4); }
 
 // Householder QR of the column-major m x n matrix A (leading dimension ld):
 // the upper triangle receives R, the part below the diagonal the reflector
@@ -400,27 +449,30 @@ __device__ __forceinline__ int row_owner(int r, int m) { return r / ((m + 3) / 4
 // alternate steps.  Two workgroup barriers per column.
 __device__ void hh_qr(double* A, int m, int n, int ld, double* tau, double* pw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int k = min(m, n);
+  const int k = min(m, n), B = (m + 3) / 4;
   double* pn = pw + 8 * (n + 1);
   for (int j = 0; j < k; ++j) {
     double* aj = A + (int64_t)j * ld;
     double* pd = pw + (j & 1) * 4 * (n + 1);
-    const bool diag = row_owner(j, m) == w;    // this wavefront holds row j
+    const bool diag = j >= w * B && j < (w + 1) * B;    // this wavefront holds row j
     int r0, r1;
     row_block(j, m, w, r0, r1);
     double s = 0.0;
     for (int r = r0 + lane; r < r1; r += 64) s = fma(aj[r], aj[r], s);
-    s = wave_sum(s);
+    s = wave_sum_dpp(s);
     if (lane == 0) pn[w] = s;
     __syncthreads();
     const double nrm2 = (pn[0] + pn[1]) + (pn[2] + pn[3]);
     const double alpha = aj[j];
     double t = 0.0, beta = alpha, inv = 0.0;
     if (nrm2 > 0.0) {
-      const double sigma = sqrt(alpha * alpha + nrm2);
+      // sigma = sqrt(alpha^2 + |x|^2) and the two quotients from the hardware
+      // reciprocal square root and reciprocal, each refined by Newton steps
+      const double s2 = fma(alpha, alpha, nrm2);
+      const double sigma = s2 * rsq_nr(s2);
       beta = alpha >= 0.0 ? -sigma : sigma;
-      t = (beta - alpha) / beta;
-      inv = 1.0 / (alpha - beta);
+      t = (beta - alpha) * rcp_nr(beta);
+      inv = rcp_nr(alpha - beta);
     }
     for (int r = r0 + lane; r < r1; r += 64) aj[r] *= inv;
     // partial w_c over this wavefront's rows (the implicit 1 of v_j meets row j)
@@ -452,12 +504,12 @@ __device__ void hh_qr(double* A, int m, int n, int ld, double* tau, double* pw) 
 // never read before, so they need no zeroing.  pw as in hh_qr.
 __device__ void hh_form_q(double* A, int m, int n, int ld, const double* tau, double* pw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int k = min(m, n);
+  const int k = min(m, n), B = (m + 3) / 4;
   for (int j = k - 1; j >= 0; --j) {
     double* aj = A + (int64_t)j * ld;
     double* pd = pw + (j & 1) * 4 * (n + 1);
     const double t = tau[j];
-    const bool diag = row_owner(j, m) == w;
+    const bool diag = j >= w * B && j < (w + 1) * B;
     int r0, r1;
     row_block(j, m, w, r0, r1);
     // row j of the columns c > j is still zero here: only rows below j count
@@ -511,33 +563,6 @@ __global__ __launch_bounds__(WS) void qr_lds_kernel(const double* __restrict__ A
   }
 }
 
-// One DPP lane exchange of a double (two 32-bit moves).
-template <int Ctrl>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, Ctrl, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, Ctrl, 0xF, 0xF, false);
-  return __hiloint2double(h2, l2);
-}
-
-// 1/x and 1/sqrt(x) from the hardware approximations refined by two Newton
-// steps each (x finite, nonzero; x > 0 for the square root), accurate to the
-// last bits for the rotation parameters of the Jacobi sweeps.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double e = fma(-h * y, y, 0.5);
-  y = fma(y, e, y);
-  e = fma(-h * y, y, 0.5);
-  return fma(y, e, y);
-}
 
 // ---------------------------------------------------------------------------
 // Register-resident Gauss-Jordan solve for systems up to a few hundred
