@@ -67,16 +67,24 @@ struct SArgs {
 // Grid barrier for a cooperative launch: the workgroup barrier makes every
 // wave's stores complete in the workgroup's L2, then one thread writes the L2
 // back to the agent coherence point (release at agent scope, which orders the
-// whole workgroup's earlier stores), counts in and waits for the epoch.
+// whole workgroup's earlier stores) and counts in.  The last to arrive
+// publishes the epoch in a flag 128 bytes past the count, on a cache line of
+// its own, which the others poll: polling the count itself slowed the
+// arrivals' atomics (about 0.8 us of a 3 us barrier at 36 workgroups).
 // Readers of data from other workgroups use ld_coherent.
 __device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target) {
+  unsigned* flag = ctr + 32;
   target += gridDim.x;
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-      __builtin_amdgcn_s_sleep(1);
+    const unsigned old = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == target) {
+      __hip_atomic_store(flag, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+        __builtin_amdgcn_s_sleep(1);
+    }
   }
   __syncthreads();
 }
@@ -1043,7 +1051,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.Pd1 = take((int64_t)p.G * (p.m + 1));
   a.Pd2 = take((int64_t)p.G * (p.m + 1));
   a.Pn = take(2 * (int64_t)p.G);
-  double* barslot = take(8);
+  double* barslot = take(32);   // the count, and 128 bytes on the epoch flag
   a.bar = reinterpret_cast<unsigned*>(barslot);
   a.m = p.m;
   a.max_iter = max_iter;
@@ -1065,7 +1073,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
     to_f32_kernel<<<(int)std::min<int64_t>(1024, (nr + 255) / 256), 256, 0, s>>>(phiR, r32, nr);
     TT_HIP(hipGetLastError());
   }
-  fill(s, barslot, 1, 0.0);
+  fill(s, barslot, 17, 0.0);
   ++g_launches;
   hipEvent_t pe = nullptr;
   if (g_probe) pe = g_probe->begin(s, kProbeKrylov, 0.0, 0.0);   // work amended after the run
