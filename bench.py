@@ -33,8 +33,8 @@ PEAK_FP64_TFLOPS = 78.6
 # valid only while the kernel's sources are unchanged.
 MEASURED_TRAFFIC = {
     ("krylov", "inner_box_n32_G4_S4"): dict(
-        bytes_per_launch=19.55e6,
-        sources={"paper_2309_03347_amd/csrc/krylov.hip": "005096eb463fa82b",
+        bytes_per_launch=19.35e6,
+        sources={"paper_2309_03347_amd/csrc/krylov.hip": "d41a4ce71ddb971a",
                  "paper_2309_03347_amd/csrc/gemm_tile.h": "8641b1e5a94501dd"}),
 }
 
