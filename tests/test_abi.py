@@ -94,6 +94,19 @@ def test_local_solve_rejects_non_square():
     assert st == native.TT_E_ARG
 
 
+def test_local_solve_rejects_unknown_method():
+    lib = native.lib()
+    sysd = native.TTLocal(2, 1, 3, 3, 1, 2, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), ctypes.c_void_p(8))
+    info = native.TTSolveInfo()
+    for method in (-1, 5):
+        opts = native.TTSolveOpts(method, 1e-10, 10, 10, 64)
+        st = lib.tt_local_solve(ctypes.byref(sysd), ctypes.c_void_p(8), ctypes.byref(opts),
+                                ctypes.byref(info), ctypes.c_void_p(8), 1 << 30, None)
+        assert st == native.TT_E_ARG, method
+        assert b"method" in native.lib().tt_last_error()
+
+
 def test_solver_rejects_bad_options():
     lib = native.lib()
     H, kh = _host_mat([2], [2], [1, 1])
