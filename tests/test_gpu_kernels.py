@@ -50,6 +50,8 @@ def _inflate(rng, x):
     ((2,) * 6, (2, 3, 4, 3, 2)),
     ((4, 3, 2, 2, 5), (3, 5, 4, 3)),
     ((8,) + (2,) * 9, (6, 9, 12, 14, 12, 9, 6, 4, 2)),
+    # inflated ranks up to 66: SVDs with 4 lanes per Jacobi pair
+    ((4,) * 6, (3, 9, 22, 9, 3)),
 ])
 def test_round_recovers_exact_ranks(cuda, modes, ranks):
     from paper_2309_03347_amd import native
