@@ -71,11 +71,15 @@ int thin_svd(hipStream_t s, const double* W, int rows, int cols, double* Lft, do
              double* RtT, const SvdScratch& sc) {
   if (rows >= cols) {
     const int p = cols;
+    // V^T written straight into RtT (p x cols)
+    if (svd_t(s, W, rows, cols, cols, 1, Lft, p, 1, S, RtT, 1, cols)) return p;
     svd(s, const_cast<double*>(W), rows, cols, cols, Lft, p, S, sc.V, p, sc.work);
     transpose(s, sc.V, p, p, p, RtT, cols);
     return p;
   }
   const int p = rows;
+  // the SVD of W^T (cols x rows) read through strides, its U^T written into RtT
+  if (svd_t(s, W, cols, rows, 1, cols, RtT, 1, cols, S, Lft, p, 1)) return p;
   transpose(s, W, rows, cols, cols, sc.G, rows);               // G = W^T (cols x rows)
   svd(s, sc.G, cols, rows, rows, sc.U, rows, S, Lft, p, sc.work);  // U: cols x rows
   transpose(s, sc.U, cols, rows, rows, RtT, cols);             // RtT = U^T (rows x cols)
@@ -252,9 +256,12 @@ void orth_right(hipStream_t s, TTv& x, Bump& ws) {
   for (int k = d - 1; k >= 1; --k) {
     const int rows = x.r[k], cols = x.n[k] * x.r[k + 1];
     const int q = std::min(rows, cols);
-    transpose(s, x.core(k), rows, cols, cols, Wt, rows);      // cols x rows
-    qr(s, Wt, cols, rows, rows, Q, q, R, rows, tau);           // Q: cols x q, R: q x rows
-    transpose(s, Q, cols, q, q, x.core(k), cols);              // core k = Q^T (q x cols)
+    // QR of core k^T (cols x rows); core k = Q^T (q x cols), written in place
+    if (!qr_t(s, x.core(k), cols, rows, 1, cols, x.core(k), 1, cols, R, rows)) {
+      transpose(s, x.core(k), rows, cols, cols, Wt, rows);      // cols x rows
+      qr(s, Wt, cols, rows, rows, Q, q, R, rows, tau);           // Q: cols x q, R: q x rows
+      transpose(s, Q, cols, q, q, x.core(k), cols);              // core k = Q^T (q x cols)
+    }
     const int prow = x.r[k - 1] * x.n[k - 1];
     gemm(s, false, true, prow, q, rows, 1.0, x.core(k - 1), rows, 0, R, rows, 0, 0.0, tmp, q, 0);
     copy(s, tmp, x.core(k - 1), (int64_t)prow * q);

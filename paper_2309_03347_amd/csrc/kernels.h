@@ -46,6 +46,16 @@ void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, dou
 void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
          double* V, int ldv, double* work);
 size_t svd_work_doubles(int m, int n);
+// The LDS-resident QR and SVD with strided operands: element (i, c) of the
+// input at A[i ars + c acs] (G[i gr + c gc]), Q(i, c) written to
+// Q[i qrs + c qcs], U(i, j) to U[i ur + j uc], V(e, j) to V[e vr + j vc]; a
+// transposed operand or result then needs no transpose launch.  The input is
+// read before any output is written (Q may overlap A).  Return false, having
+// launched nothing, when the matrix does not fit in LDS.
+bool qr_t(hipStream_t s, const double* A, int m, int n, int64_t ars, int64_t acs, double* Q,
+          int64_t qrs, int64_t qcs, double* R, int ldr);
+bool svd_t(hipStream_t s, const double* G, int m, int n, int64_t gr, int64_t gc, double* U,
+           int64_t ur, int64_t uc, double* S, double* V, int64_t vr, int64_t vc);
 // Truncation rank: smallest r with sqrt(sum_{i>=r} S_i^2) <= delta, where
 // delta = tol * sqrt(*normsq) / sqrt(dm1) (or tol * ||S|| when normsq == NULL);
 // r capped to [1, rmax]; writes rank[0] (device int), rank[1] = 1 if rmax bound, and adds the discarded

@@ -534,18 +534,23 @@ __device__ void hh_form_q(double* A, int m, int n, int ld, const double* tau, do
 }
 
 // QR with diag(R) >= 0: Q (m x k), R (k x n), k = min(m, n); A row-major.
-__global__ __launch_bounds__(WS) void qr_lds_kernel(const double* __restrict__ Ag, int m, int n,
-                                                    int ldag, double* __restrict__ Qg, int ldq,
-                                                    double* __restrict__ R, int ldr) {
+// Element (i, c) of the input is Ag[i ars + c acs] and element (i, c) of Q
+// is written to Qg[i qrs + c qcs], so a transposed operand or result needs no
+// separate transpose (the input is fully read into LDS before Q is written,
+// so Qg may overlap Ag).
+__global__ __launch_bounds__(WS) void qr_lds_kernel(const double* Ag, int m, int n, int64_t ars,
+                                                    int64_t acs, double* Qg, int64_t qrs,
+                                                    int64_t qcs, double* __restrict__ R, int ldr) {
   extern __shared__ double sm[];
   const int ld = odd_ld(m), k = min(m, n), tid = threadIdx.x;
   double* A = sm;
   double* tau = A + (int64_t)ld * n;
   double* sg = tau + k;
   double* pw = sg + k;
+  const bool rfast = ars == 1;   // walk the index whose stride is 1 fastest
   for (int e = tid; e < m * n; e += WS) {
-    const int i = e / n, c = e % n;
-    A[(int64_t)c * ld + i] = Ag[(int64_t)i * ldag + c];
+    const int i = rfast ? e % m : e / n, c = rfast ? e / m : e % n;
+    A[(int64_t)c * ld + i] = Ag[(int64_t)i * ars + (int64_t)c * acs];
   }
   __syncthreads();
   hh_qr(A, m, n, ld, tau, pw);
@@ -557,9 +562,10 @@ __global__ __launch_bounds__(WS) void qr_lds_kernel(const double* __restrict__ A
   }
   __syncthreads();
   hh_form_q(A, m, n, ld, tau, pw);
+  const bool qfast = qrs == 1;
   for (int e = tid; e < m * k; e += WS) {
-    const int i = e / k, c = e % k;
-    Qg[(int64_t)i * ldq + c] = sg[c] * A[(int64_t)c * ld + i];
+    const int i = qfast ? e % m : e / k, c = qfast ? e / m : e % k;
+    Qg[(int64_t)i * qrs + (int64_t)c * qcs] = sg[c] * A[(int64_t)c * ld + i];
   }
 }
 
@@ -774,11 +780,16 @@ __device__ __forceinline__ double group_sum(double v) {
 // U = Q W and V = Y diag(1 / |Y_j|).  Singular values sorted descending;
 // each column of U has its largest-magnitude entry positive.  LP lanes serve
 // one Jacobi pair (the largest power of two with LP (n + 1) / 2 <= 256).
+// Element (i, c) of G is Gg[i grs + c gcs]; U(i, j) goes to U[i urs + j ucs]
+// and V(e, j) to V[e vrs + j vcs], so transposed operands and results need no
+// separate transposes.
 template <int LP>
 __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ Gg, int m, int n,
-                                                     int ldg, double* __restrict__ U, int ldu,
-                                                     double* __restrict__ S,
-                                                     double* __restrict__ V, int ldv) {
+                                                     int64_t grs, int64_t gcs,
+                                                     double* __restrict__ U, int64_t urs,
+                                                     int64_t ucs, double* __restrict__ S,
+                                                     double* __restrict__ V, int64_t vrs,
+                                                     int64_t vcs) {
   extern __shared__ double sm[];
   __shared__ int s_rot, s_big;
   __shared__ double s_fro;
@@ -790,9 +801,10 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
   double* sig = tau + n;                        // n
   double* rk = sig + n;                         // n
   double* pw = rk + n;                          // 8 (n + 1) + 4
+  const bool rfast = grs == 1;
   for (int e = tid; e < m * n; e += WS) {
-    const int i = e / n, c = e % n;
-    A[(int64_t)c * ld + i] = Gg[(int64_t)i * ldg + c];
+    const int i = rfast ? e % m : e / n, c = rfast ? e / m : e % n;
+    A[(int64_t)c * ld + i] = Gg[(int64_t)i * grs + (int64_t)c * gcs];
   }
   __syncthreads();
   hh_qr(A, m, n, ld, tau, pw);
@@ -941,18 +953,18 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int i = lane + 64 * t;
-      if (i < m) U[(int64_t)i * ldu + j] = sgn * uv[t];
+      if (i < m) U[(int64_t)i * urs + (int64_t)j * ucs] = sgn * uv[t];
     }
     for (int i0 = 256; i0 < m; i0 += 64) {
       const int i = i0 + lane;
       if (i < m) {
         double acc = 0.0;
         for (int kk = 0; kk < n; ++kk) acc = fma(A[(int64_t)kk * ld + i], wc[kk], acc);
-        U[(int64_t)i * ldu + j] = sgn * acc;
+        U[(int64_t)i * urs + (int64_t)j * ucs] = sgn * acc;
       }
     }
     const double inv = sp > 0.0 ? sgn / sp : 0.0;
-    for (int e = lane; e < n; e += 64) V[(int64_t)e * ldv + j] = Y[(int64_t)c * ldn + e] * inv;
+    for (int e = lane; e < n; e += 64) V[(int64_t)e * vrs + (int64_t)j * vcs] = Y[(int64_t)c * ldn + e] * inv;
     if (lane == 0) S[j] = sp;
   }
 }
@@ -999,15 +1011,21 @@ int lds_limit() {
 
 }  // namespace
 
+bool qr_t(hipStream_t s, const double* A, int m, int n, int64_t ars, int64_t acs, double* Q,
+          int64_t qrs, int64_t qcs, double* R, int ldr) {
+  if (m <= 0 || n <= 0) return true;
+  if (qr_lds_doubles(m, n) * 8 > (size_t)lds_limit()) return false;
+  ++g_launches;
+  qr_lds_kernel<<<1, WS, qr_lds_doubles(m, n) * 8, s>>>(A, m, n, ars, acs, Q, qrs, qcs, R, ldr);
+  TT_HIP(hipGetLastError());
+  return true;
+}
+
 void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R, int ldr,
         double* tau) {
   if (m <= 0 || n <= 0) return;
+  if (qr_t(s, A, m, n, lda, 1, Q, ldq, 1, R, ldr)) return;
   ++g_launches;
-  if (qr_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
-    qr_lds_kernel<<<1, WS, qr_lds_doubles(m, n) * 8, s>>>(A, m, n, lda, Q, ldq, R, ldr);
-    TT_HIP(hipGetLastError());
-    return;
-  }
   const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
   qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
       A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
@@ -1016,28 +1034,35 @@ void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, dou
 
 size_t svd_work_doubles(int m, int n) { return (size_t)n * m + (size_t)n * n + 2 * (size_t)n; }
 
-void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
-         double* V, int ldv, double* work) {
-  if (m <= 0 || n <= 0) return;
+bool svd_t(hipStream_t s, const double* G, int m, int n, int64_t gr, int64_t gc, double* U,
+           int64_t ur, int64_t uc, double* S, double* V, int64_t vr, int64_t vc) {
+  if (m <= 0 || n <= 0) return true;
   TT_REQUIRE(m >= n, "svd expects m >= n");
-  ++g_launches;
   // lanes per Jacobi pair: the largest power of two (at most 64) that lets
   // all (n + 1) / 2 pairs of a round run at once in 256 threads
   const int npair = (n + 1) / 2;
   int lp = 64;
   while (lp > 4 && npair * lp > WS) lp >>= 1;
-  if (npair * lp <= WS && svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit()) {
-    const size_t lds = svd_lds_doubles(m, n) * 8;
-    switch (lp) {
-      case 64: svd_lds_kernel<64><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
-      case 32: svd_lds_kernel<32><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
-      case 16: svd_lds_kernel<16><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
-      case 8: svd_lds_kernel<8><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
-      default: svd_lds_kernel<4><<<1, WS, lds, s>>>(G, m, n, ldg, U, ldu, S, V, ldv); break;
-    }
-    TT_HIP(hipGetLastError());
-    return;
+  if (npair * lp > WS || svd_lds_doubles(m, n) * 8 > (size_t)lds_limit()) return false;
+  ++g_launches;
+  const size_t lds = svd_lds_doubles(m, n) * 8;
+  switch (lp) {
+    case 64: svd_lds_kernel<64><<<1, WS, lds, s>>>(G, m, n, gr, gc, U, ur, uc, S, V, vr, vc); break;
+    case 32: svd_lds_kernel<32><<<1, WS, lds, s>>>(G, m, n, gr, gc, U, ur, uc, S, V, vr, vc); break;
+    case 16: svd_lds_kernel<16><<<1, WS, lds, s>>>(G, m, n, gr, gc, U, ur, uc, S, V, vr, vc); break;
+    case 8: svd_lds_kernel<8><<<1, WS, lds, s>>>(G, m, n, gr, gc, U, ur, uc, S, V, vr, vc); break;
+    default: svd_lds_kernel<4><<<1, WS, lds, s>>>(G, m, n, gr, gc, U, ur, uc, S, V, vr, vc); break;
   }
+  TT_HIP(hipGetLastError());
+  return true;
+}
+
+void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
+         double* V, int ldv, double* work) {
+  if (m <= 0 || n <= 0) return;
+  TT_REQUIRE(m >= n, "svd expects m >= n");
+  if (svd_t(s, G, m, n, ldg, 1, U, ldu, 1, S, V, ldv, 1)) return;
+  ++g_launches;
   const size_t need = svd_work_doubles(m, n);
   const bool lds = need <= (size_t)kLdsDoubles;
   svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);

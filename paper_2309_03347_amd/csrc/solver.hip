@@ -456,13 +456,17 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   int p;
   if (rows >= cols) {
     p = cols;
-    svd(s, xloc, rows, cols, cols, Lft, p, Sv, sV, p, sWk);
-    transpose(s, sV, p, p, p, RtT, cols);
+    if (!svd_t(s, xloc, rows, cols, cols, 1, Lft, p, 1, Sv, RtT, 1, cols)) {
+      svd(s, xloc, rows, cols, cols, Lft, p, Sv, sV, p, sWk);
+      transpose(s, sV, p, p, p, RtT, cols);
+    }
   } else {
     p = rows;
-    transpose(s, xloc, rows, cols, cols, sG, rows);
-    svd(s, sG, cols, rows, rows, sU, rows, Sv, Lft, p, sWk);
-    transpose(s, sU, cols, rows, rows, RtT, cols);
+    if (!svd_t(s, xloc, cols, rows, 1, cols, RtT, 1, cols, Sv, Lft, p, 1)) {
+      transpose(s, xloc, rows, cols, cols, sG, rows);
+      svd(s, sG, cols, rows, rows, sU, rows, Sv, Lft, p, sWk);
+      transpose(s, sU, cols, rows, rows, RtT, cols);
+    }
   }
   trunc_rank(s, Sv, p, tol, (double)d, nullptr, rmax, irank, nullptr);
   TT_HIP(hipMemcpyAsync(hb.i, irank, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
