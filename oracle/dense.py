@@ -6,7 +6,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
    (eq. Discretized_kNTE) and the vacuum boundary equations
    (eq. discreteBCs).  The equation of cell c for direction l sits at the row
    of c's outgoing vertex; a boundary equation psi = 0 sits at its inflow
-   face node.
+   face node.  Optionally, periodic axes: the inflow-face row becomes
+   psi(node) = psi(opposite-face node) (an infinite-medium mode the paper
+   does not have; it gives the closed-form pins at any grid size).
 2. ``appendix_cell_rows``: the cell rows rebuilt from the appendix
    matricization (difference matrix D_x, averaging matrix S_x, Kronecker
    products, zeroth angular moment for isotropic scattering).
@@ -22,6 +24,14 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 ``k_dominant`` is the brute-force generalized eigensolve: the largest
 eigenvalue of (H - S)^{-1} F.
+
+Pins (tests/test_oracle_sweep.py, tests/test_oracle_pins.py): the three
+assemblies agree row by row; the boundary-row count is the appendix's; the
+equation-row H equals the sweep; one LU step equals the sweep checker's
+step; with periodic faces (a homogeneous infinite medium) one step from a
+constant flux gives k_1 = k_0 sigma_s/sigma_t + nu_sigma_f/sigma_t and a
+constant flux, and the brute-force k is nu_sigma_f/(sigma_t - sigma_s) (one
+group) or nu_sigma_f^T (diag sigma_t - Sigma_s)^{-1} chi (several groups).
 """
 from __future__ import annotations
 
@@ -40,10 +50,19 @@ def _node(n, k, j, i):
     return (k * n + j) * n + i
 
 
-def equation_operators(wl):
-    """H, S, F (CSR) in the equation-row arrangement, unknowns psi[g,l,k,j,i]."""
+def equation_operators(wl, periodic=None):
+    """H, S, F (CSR) in the equation-row arrangement, unknowns psi[g,l,k,j,i].
+
+    ``periodic`` (per axis z, y, x; default: ``wl.periodic``) replaces the
+    vacuum row psi = 0 of an incoming-face node on that axis by
+    psi(node) - psi(node on the opposite face) = 0.  A node on several
+    incoming faces takes the condition of the x face first, then y, then z.
+    """
     n, M, h = _grid(wl)
     G, L = wl.G, wl.L
+    if periodic is None:
+        periodic = getattr(wl, "periodic", (False, False, False))
+    per_z, per_y, per_x = (bool(p) for p in periodic)
     N = n ** 3
     mat = wl.cell_material()
     q = wl.quad
@@ -63,6 +82,14 @@ def equation_operators(wl):
                         if i == i_in or j == j_in or k == k_in:
                             r = base + _node(n, k, j, i)
                             Hr.append(r); Hc.append(r); Hv.append(1.0)
+                            if i == i_in:
+                                opp = _node(n, k, j, n - 1 - i) if per_x else None
+                            elif j == j_in:
+                                opp = _node(n, k, n - 1 - j, i) if per_y else None
+                            else:
+                                opp = _node(n, n - 1 - k, j, i) if per_z else None
+                            if opp is not None:
+                                Hr.append(r); Hc.append(base + opp); Hv.append(-1.0)
             for ck in range(1, n):
                 for cj in range(1, n):
                     for ci in range(1, n):
@@ -284,16 +311,3 @@ def k_dominant(H, S, F, dense: bool = False) -> float:
     op = spla.LinearOperator(A.shape, matvec=lambda x: lu.solve(F @ x), dtype=np.float64)
     ev = spla.eigs(op, k=1, which="LM", tol=1e-14, maxiter=20000, return_eigenvectors=False)
     return float(ev[0].real)
-
-
-def k_dominant_vector(H, S, F):
-    """(k, eigenvector) of (H - S)^{-1} F by ARPACK; eigenvector unit norm, positive sum."""
-    A = (H - S).tocsc()
-    lu = spla.splu(A)
-    op = spla.LinearOperator(A.shape, matvec=lambda x: lu.solve(F @ x), dtype=np.float64)
-    ev, vec = spla.eigs(op, k=1, which="LM", tol=1e-14, maxiter=20000)
-    v = vec[:, 0].real
-    v /= np.linalg.norm(v)
-    if v.sum() < 0:
-        v = -v
-    return float(ev[0].real), v

@@ -4,8 +4,14 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Pins (tests/test_oracle_sweep.py):
   * reflective homogeneous cube: k -> nu_sigma_f/(sigma_t - sigma_s) (one
-    group) or nu_sigma_f^T (diag sigma_t - Sigma_s)^{-1} chi (many groups), and
-    from a constant start the error contracts by exactly sigma_s/sigma_t;
+    group) or nu_sigma_f^T (diag sigma_t - Sigma_s)^{-1} chi (many groups);
+    the reflection here is lagged (incoming faces from the previous iterate),
+    so only the limit is the closed form; its limit equals the eigenvalue of
+    the dense operator with mirror rows (tests/test_oracle_pins.py);
+  * one power step equals H^{-1}(S + F/k) psi by a sparse LU of the dense
+    equation-row operator, with k from sum(F psi) of the dense F; the
+    fission functional equals sum(F psi) for all three dense assemblies;
+    the source equals the cell rows of (S + F/k) psi;
   * the sweep equals a dense LU solve of the equation-row operator;
   * the converged k equals the brute-force generalized eigenvalue;
   * neutron balance: leakage + absorption = in-scatter + production / k;
@@ -27,10 +33,13 @@ _LIB = os.path.join(_HERE, "libddsweep.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile the checker with gcc (plain C, OpenMP over (group, direction))."""
+    """Compile the checker with gcc (plain C, OpenMP over (group, direction)).
+
+    -march=x86-64-v3 (AVX2, FMA) rather than native, so that the library
+    built on one host also runs on any other recent x86-64 host."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
                                _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

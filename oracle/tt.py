@@ -7,9 +7,10 @@ Definitions follow Section 2.2 and appendix B:
     (eq. TT-vector), row-major over (i_1, ..., i_d);
   * ``full_mat``: A((i),(j)) = A_1(i_1,j_1) ... A_d(i_d,j_d)
     (eq. TT-matrix-compact), i.e. the Kronecker product for rank 1;
-  * ``matvec``: y = A x on the reconstructions;
-  * ``round_check``: the rounding contract - ||X - Y|| <= tol ||X|| when the
-    rank cap does not bind, from dense reconstructions;
+  * ``matvec``: y = A x on the reconstructions; ``dot``: <a, b> on them;
+  * ``round_error_bound``: the relative error ||X - Y|| / ||X|| of a rounding,
+    from dense reconstructions (the contract is <= tol when the rank cap does
+    not bind);
   * ``unfolding_svals``: singular values of the k-th unfolding (library SVD);
   * ``local_matrix``: the projected local operator of the alternating solve,
     Phi_L (x) A_k (x) Phi_R written as an explicit sum of Kronecker products
@@ -21,7 +22,10 @@ Definitions follow Section 2.2 and appendix B:
 Pins (tests/test_oracle_tt.py): rank-1 reconstructions equal numpy.kron;
 QTT of exp(a x) has rank 1 and of sin(a x) rank 2; a matvec of Kronecker
 operators equals the Kronecker product applied to a dense vector; the local
-matrix of a chain whose interfaces are identities equals the full operator.
+matrix of a chain whose interfaces are identities equals the full operator,
+and with orthonormal interfaces it equals P^T A P; ``dot`` of two rank-1
+trains is the product of the factor inner products; the unfolding singular
+values of a random train vanish beyond its ranks.
 """
 from __future__ import annotations
 
@@ -50,10 +54,6 @@ def full_mat(cores: Sequence[np.ndarray]) -> np.ndarray:
 
 def matvec(A_cores, x_cores) -> np.ndarray:
     return full_mat(A_cores) @ full_vec(x_cores)
-
-
-def norm(cores) -> float:
-    return float(np.linalg.norm(full_vec(cores)))
 
 
 def dot(a_cores, b_cores) -> float:
@@ -152,26 +152,6 @@ def local_matrix(phiL: np.ndarray, Ak: np.ndarray, phiR: np.ndarray) -> np.ndarr
         for bp in range(R1):
             out += np.kron(np.kron(phiL[:, b, :], Ak[b, :, :, bp]), phiR[:, bp, :])
     return out
-
-
-def local_rhs(phiL_B: np.ndarray, Bk: np.ndarray, phiR_B: np.ndarray) -> np.ndarray:
-    """f[a, i, c] = sum PhiL_B[a, b] B_k[b, i, b'] PhiR_B[c, b']."""
-    return np.einsum("ab,bic,dc->aid", phiL_B, Bk, phiR_B).reshape(-1)
-
-
-def vec_left_interface(x_cores, b_cores, k: int) -> np.ndarray:
-    """Phi_L_B[a, b] = X_<k[:, a] . B_<k[:, b] on reconstructions."""
-    if k == 0:
-        return np.ones((1, 1))
-    return _partial(x_cores[:k]).T @ _partial(b_cores[:k])
-
-
-def vec_right_interface(x_cores, b_cores, k: int) -> np.ndarray:
-    """Phi_R_B[a, b] = X_>k[a, :] . B_>k[b, :] on reconstructions."""
-    d = len(x_cores)
-    if k == d - 1:
-        return np.ones((1, 1))
-    return _partial_right(x_cores[k + 1:]) @ _partial_right(b_cores[k + 1:]).T
 
 
 def qtt_of_function(values: np.ndarray, tol: float = 1e-12) -> List[np.ndarray]:

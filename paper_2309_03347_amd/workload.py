@@ -75,7 +75,8 @@ class Workload:
     tol: float
     tol_k: float
     seed: int
-    boundary: str = "vacuum"    # "vacuum", or "reflective" (checker-only closed-form mode)
+    boundary: str = "vacuum"    # "vacuum", or "reflective" (lagged mirror faces, sweep checker only)
+    periodic: tuple = (False, False, False)   # per axis (z, y, x): inflow face = opposite face
 
     @property
     def n(self) -> int:

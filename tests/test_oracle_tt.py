@@ -98,3 +98,12 @@ def test_round_error_helper():
     b = a.copy()
     b[0] += 0.1
     assert abs(OT.round_error_bound(a, b) - 0.1 / np.sqrt(10)) < 1e-15
+
+
+def test_dot_of_rank_one_trains_is_product_of_factor_dots():
+    rng = np.random.default_rng(6)
+    a = [rng.standard_normal(n) for n in (3, 2, 5)]
+    b = [rng.standard_normal(n) for n in (3, 2, 5)]
+    ref = np.prod([x @ y for x, y in zip(a, b)])
+    got = OT.dot([v.reshape(1, -1, 1) for v in a], [v.reshape(1, -1, 1) for v in b])
+    assert abs(got - ref) < 1e-13 * max(1.0, abs(ref))
