@@ -166,6 +166,17 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts);
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
                          tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream);
 
+
+/*
+ * ttnt_set_grid_wait_limit - how long (seconds, default 20) a workgroup of a
+ * persistent local solve waits at a grid barrier before it gives up.  A solve
+ * whose workgroups gave up returns TT_E_HIP instead of hanging (for example
+ * if a cooperative grid could not be resident at once).  Applies to launches
+ * issued after the call, process-wide.  A limit <= 0 makes the first wait
+ * give up (used to test the error path).  TT_E_ARG for NaN.
+ */
+tt_status ttnt_set_grid_wait_limit(double seconds);
+
 /*
  * Power-iteration solver (one call of tt_power_step = one step of
  * eq. TT_k_eff_fixed_points).

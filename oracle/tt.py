@@ -15,6 +15,8 @@ Definitions follow Section 2.2 and appendix B:
   * ``local_matrix``: the projected local operator of the alternating solve,
     Phi_L (x) A_k (x) Phi_R written as an explicit sum of Kronecker products
     over the operator rank indices;
+  * ``local_apply``: the same operator applied to a vector without forming it
+    (for systems too large for the explicit matrix);
   * ``left_interface``/``right_interface``: the projections of A onto the
     left/right orthonormal parts of X, computed on the reconstructions of the
     partial trains (no core-wise recursion).
@@ -23,7 +25,8 @@ Pins (tests/test_oracle_tt.py): rank-1 reconstructions equal numpy.kron;
 QTT of exp(a x) has rank 1 and of sin(a x) rank 2; a matvec of Kronecker
 operators equals the Kronecker product applied to a dense vector; the local
 matrix of a chain whose interfaces are identities equals the full operator,
-and with orthonormal interfaces it equals P^T A P; ``dot`` of two rank-1
+and with orthonormal interfaces it equals P^T A P; ``local_apply`` equals
+``local_matrix`` times the vector; ``dot`` of two rank-1
 trains is the product of the factor inner products; the unfolding singular
 values of a random train vanish beyond its ranks.
 """
@@ -152,6 +155,19 @@ def local_matrix(phiL: np.ndarray, Ak: np.ndarray, phiR: np.ndarray) -> np.ndarr
         for bp in range(R1):
             out += np.kron(np.kron(phiL[:, b, :], Ak[b, :, :, bp]), phiR[:, bp, :])
     return out
+
+
+def local_apply(phiL: np.ndarray, Ak: np.ndarray, phiR: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """The local operator applied to x[a', j, c'] without forming it:
+    y[a, i, c] = sum PhiL[a, b, a'] A_k[b, i, j, b'] PhiR[c, b', c'] x[a', j, c']."""
+    rL = phiL.shape[0]
+    n = Ak.shape[2]
+    rR = phiR.shape[0]
+    X = x.reshape(rL, n, rR)
+    y = np.einsum("aBp,pjc->aBjc", phiL, X)          # contract a'
+    y = np.einsum("aBjc,Bijd->aidc", y, Ak)          # contract b, j
+    y = np.einsum("aidc,edc->aie", y, phiR)          # contract b', c'
+    return y.reshape(-1)
 
 
 def qtt_of_function(values: np.ndarray, tol: float = 1e-12) -> List[np.ndarray]:

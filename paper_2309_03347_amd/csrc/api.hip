@@ -4,6 +4,7 @@
 #include <thread>
 #include <cmath>
 #include <exception>
+#include <mutex>
 #include <string>
 
 #include "engine.h"
@@ -100,6 +101,36 @@ LocalSolveOpts solve_opts_from(const tt_solve_opts* o) {
     so.mixed = o->precision == 1;
   }
   return so;
+}
+
+void local_solve_impl(const tt_local* sys, double* x, const tt_solve_opts* opts,
+                      tt_solve_info* info, void* ws, size_t ws_bytes, hipStream_t s) {
+  TT_REQUIRE(sys && x && ws, "NULL system, x or workspace");
+  TT_REQUIRE(sys->phiL && sys->A && sys->phiR && sys->f, "NULL field in system");
+  TT_REQUIRE(sys->ra >= 1 && sys->RL >= 1 && sys->m >= 1 && sys->n >= 1 && sys->RR >= 1 &&
+                 sys->rc >= 1,
+             "dimensions must be >= 1");
+  TT_REQUIRE(sys->m == sys->n, "local operator must be square (m == n)");
+  LocalSolveOpts so = solve_opts_from(opts);
+  TT_REQUIRE(so.method >= 0 && so.method <= 4, "method must be 0, 1, 2, 3 or 4");
+  if (ws_bytes < tt_local_solve_workspace(sys, opts))
+    throw CapacityError{"workspace smaller than tt_local_solve_workspace"};
+  Bump w;
+  w.base = (char*)ws;
+  w.cap = ws_bytes;
+  double* Ap = w.d((size_t)sys->RL * sys->m * sys->n * sys->RR);
+  permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
+  LocalOp op = local_op_from(sys);
+  op.Ap = Ap;
+  op.diag = so.method == 3;
+  LocalSolveResult r = local_solve(s, op, sys->f, x, so, w, true);
+  if (info) {
+    info->iterations = r.iterations;
+    info->method_used = r.method;
+    info->rel_res = r.rel_res;
+  }
+  if (!std::isfinite(r.rel_res)) throw NumericError{};
+  if (!r.converged) throw NoConvError{};
 }
 
 }  // namespace
@@ -204,34 +235,13 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts) 
 
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
                          tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream) {
+  return guard([&] { local_solve_impl(sys, x, opts, info, ws, ws_bytes, (hipStream_t)stream); });
+}
+
+tt_status ttnt_set_grid_wait_limit(double seconds) {
   return guard([&] {
-    TT_REQUIRE(sys && x && ws, "NULL system, x or workspace");
-    TT_REQUIRE(sys->phiL && sys->A && sys->phiR && sys->f, "NULL field in system");
-    TT_REQUIRE(sys->ra >= 1 && sys->RL >= 1 && sys->m >= 1 && sys->n >= 1 && sys->RR >= 1 &&
-                   sys->rc >= 1,
-               "dimensions must be >= 1");
-    TT_REQUIRE(sys->m == sys->n, "local operator must be square (m == n)");
-    LocalSolveOpts so = solve_opts_from(opts);
-    TT_REQUIRE(so.method >= 0 && so.method <= 4, "method must be 0, 1, 2, 3 or 4");
-    if (ws_bytes < tt_local_solve_workspace(sys, opts))
-      throw CapacityError{"workspace smaller than tt_local_solve_workspace"};
-    hipStream_t s = (hipStream_t)stream;
-    Bump w;
-    w.base = (char*)ws;
-    w.cap = ws_bytes;
-    double* Ap = w.d((size_t)sys->RL * sys->m * sys->n * sys->RR);
-    permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
-    LocalOp op = local_op_from(sys);
-    op.Ap = Ap;
-    op.diag = so.method == 3;
-    LocalSolveResult r = local_solve(s, op, sys->f, x, so, w, true);
-    if (info) {
-      info->iterations = r.iterations;
-      info->method_used = r.method;
-      info->rel_res = r.rel_res;
-    }
-    if (!std::isfinite(r.rel_res)) throw NumericError{};
-    if (!r.converged) throw NoConvError{};
+    TT_REQUIRE(seconds == seconds, "seconds is NaN");
+    krylov_set_wait_limit(seconds);
   });
 }
 

@@ -114,12 +114,15 @@ struct LocalSolveResult {
 size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o);
 // Solve (PhiL (x) A (x) PhiR) x = f; x holds the initial guess.  `final_res`
 // requests the final residual (one extra apply and a synchronization).
-// With defer_info (pinned host, 3 doubles) a persistent GMRES solve does not
-// synchronize: [iterations, converged, residual estimate] land there once the
-// stream reaches this point, and the result is marked deferred.
+// With defer_info (pinned host, 5 doubles) a persistent GMRES solve does not
+// synchronize: [iterations, converged, residual estimate, -, gave up] land
+// there once the stream reaches this point, and the result is marked deferred.
 LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, double* x,
                              const LocalSolveOpts& o, Bump& ws, bool final_res,
                              double* defer_info = nullptr);
+// Raises the error of a persistent solve whose workgroups gave up waiting at a
+// grid barrier (reported as TT_E_HIP).
+[[noreturn]] void throw_barrier_abort();
 // Work of a persistent GMRES solve (for the kernel probe), once its iteration
 // count is known.
 void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot,

@@ -318,6 +318,11 @@ size_t local_solve_ws_doubles(const LocalOp& op, const LocalSolveOpts& o) {
   return (size_t)need + 1024;
 }
 
+void throw_barrier_abort() {
+  throw HipError{hipErrorLaunchTimeOut,
+                 "persistent GMRES: a workgroup gave up waiting at a grid barrier"};
+}
+
 void krylov_probe_amend(const LocalOp& op, int restart, int iterations, int slot, bool mixed) {
   if (!g_probe || slot < 0) return;
   const KrylovShape sh{op.ra, op.RL, op.n, op.RR, op.rc};
@@ -391,13 +396,14 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
                                      o.eta, kws, kw, scal, grid, mixed, o.inner_tol);
     const int slot = probed ? g_probe->last_slot() : -1;
     if (defer_info && !final_res) {
-      TT_HIP(hipMemcpyAsync(defer_info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      TT_HIP(hipMemcpyAsync(defer_info, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
       res.deferred = true;
       res.probe_slot = slot;
     } else {
-      double info[3];
-      TT_HIP(hipMemcpyAsync(info, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      double info[5];
+      TT_HIP(hipMemcpyAsync(info, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
       TT_HIP(hipStreamSynchronize(s));
+      if (info[4] != 0.0) throw_barrier_abort();
       res.iterations = (int)info[0];
       res.converged = info[1] != 0.0;
       krylov_probe_amend(op, o.restart, res.iterations, slot, mixed);

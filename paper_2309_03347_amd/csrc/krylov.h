@@ -34,14 +34,19 @@ bool krylov_enabled();
 bool krylov_fits(const KrylovShape& sh, int restart, bool mixed = false);
 size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int grid);
 // GMRES(restart) from the initial guess in x; stops when ||r|| <= max(tol ||f||,
-// eta ||r_0||) or after max_iter Arnoldi steps.  info (device, 3 doubles)
-// receives [iterations, converged (0/1), final residual estimate / ||f||].
+// eta ||r_0||) or after max_iter Arnoldi steps.  info (device, 5 doubles)
+// receives [iterations, converged (0/1), final residual estimate / ||f||, -,
+// gave up]: info[4] is 1.0 when a workgroup gave up waiting at a grid
+// barrier (the result is then invalid), else 0.0.
 // mixed: the Arnoldi iterations run in FP32 and each restart cycle is one
 // step of iterative refinement on the FP64 residual (a cycle ends once its
 // own residual fell by inner_tol); convergence is judged on the FP64 residual.
 // One cooperative launch (plus a one-element fill of the barrier counter and,
 // when mixed, an FP32 copy of PhiR).  Returns true when the launch was
 // bracketed by the kernel probe.
+// Seconds a workgroup of the persistent kernel waits at a grid barrier before
+// it gives up (default 20; applies to launches issued afterwards).
+void krylov_set_wait_limit(double seconds);
 bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, const double* Ap,
                   const double* phiR, const double* f, double* x, int restart, int max_iter,
                   double tol, double eta, double* ws, size_t ws_doubles, double* info, int grid,

@@ -23,6 +23,7 @@
 // the iteration count is bounded by max_iter.
 #include <algorithm>
 #include <cstdlib>
+#include <atomic>
 #include <mutex>
 
 #include "gemm_tile.h"
@@ -60,8 +61,9 @@ struct SArgs {
   int m, max_iter, spw, ldv;
   double tol, eta;
   double inner_tol;     // mixed mode: an inner cycle stops at this fraction of its start residual
-  unsigned* bar;
-  double* info;         // [iterations, converged, |g_k| / ||f||]
+  unsigned* bar;        // grid barrier: count, epoch flag (+32), abort word (+48)
+  long long wait_limit; // wall-clock ticks a workgroup waits at a grid barrier before giving up
+  double* info;         // [iterations, converged, |g_k| / ||f||, -, gave up (1.0)]
 };
 
 // Grid barrier for a cooperative launch: the workgroup barrier makes every
@@ -71,9 +73,18 @@ struct SArgs {
 // publishes the epoch in a flag 128 bytes past the count, on a cache line of
 // its own, which the others poll: polling the count itself slowed the
 // arrivals' atomics (about 0.8 us of a 3 us barrier at 36 workgroups).
-// Readers of data from other workgroups use ld_coherent.
-__device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target) {
+// Readers of data from other workgroups use ld_coherent, which bypasses the
+// non-coherent cache levels, so no acquire-side invalidation is needed and
+// the operator stays cached across iterations.
+//
+// The wait is bounded: a workgroup that has waited `limit` wall-clock ticks
+// sets the abort word (64 words past the count... 48 words, its own line) and
+// leaves; every later barrier of the launch sees the word and does not wait.
+// The Arnoldi loop is bounded by max_iter, so every workgroup then runs to
+// its end and the launch drains; the host reports the abort as an error.
+__device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target, long long limit) {
   unsigned* flag = ctr + 32;
+  unsigned* abort_w = ctr + 48;
   target += gridDim.x;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -82,8 +93,15 @@ __device__ __forceinline__ void grid_sync(unsigned* ctr, unsigned& target) {
     if (old + 1 == target) {
       __hip_atomic_store(flag, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        if (wall_clock64() - t0 > limit) {
+          __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
         __builtin_amdgcn_s_sleep(1);
+      }
     }
   }
   __syncthreads();
@@ -738,7 +756,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       a.Pn[2 * b] = rr;
       a.Pn[2 * b + 1] = ff;
     }
-    grid_sync(a.bar, target);
+    grid_sync(a.bar, target, a.wait_limit);
     gather_pn(0);
     __syncthreads();
     gather_pn(1);
@@ -779,12 +797,12 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
         __syncthreads();
         dots(j, w, a.Pd1 + (int64_t)b * (m + 1));
       }
-      grid_sync(a.bar, target);
+      grid_sync(a.bar, target, a.wait_limit);
       gather(a.Pd1, j, hcol);
       orth(w, j, hcol);
       __syncthreads();
       dots(j, w, a.Pd2 + (int64_t)b * (m + 1));
-      grid_sync(a.bar, target);
+      grid_sync(a.bar, target, a.wait_limit);
       gather(a.Pd2, j, h2);
       {
         double nn = orth(w, j, h2);
@@ -793,7 +811,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
         nn = wg_sum(nn, red);
         if (tid == 0) a.Pn[2 * b] = nn;
       }
-      grid_sync(a.bar, target);
+      grid_sync(a.bar, target, a.wait_limit);
       gather_pn(0);
       __syncthreads();
       // norm, Hessenberg column, Givens rotation (every workgroup, same order)
@@ -850,19 +868,33 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       a.x[e0 + e] = acc;
     }
     if (conv || total >= a.max_iter) break;
-    grid_sync(a.bar, target);
+    grid_sync(a.bar, target, a.wait_limit);
   }
   if (b == 0 && tid == 0) {
     a.info[0] = (double)total;
     a.info[1] = conv ? 1.0 : 0.0;
     a.info[2] = fnorm > 0.0 ? res_est / fnorm : 0.0;
   }
+  // info[4] was cleared before the launch; a workgroup that saw the abort
+  // word (at least the one that set it) marks the result invalid.
+  if (tid == 0 && __hip_atomic_load(a.bar + 48, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+    a.info[4] = 1.0;
 }
 
 struct DevInfo {
   int cus = 0;
   int lds_max = 0;
+  int wall_khz = 0;     // rate of the device's constant wall clock
 };
+
+// How long a workgroup waits at a grid barrier before it gives up (seconds;
+// set by ttnt_set_grid_wait_limit, default 20 s).
+std::atomic<double> g_wait_limit_s{20.0};
+
+long long wait_limit_ticks(const DevInfo& d) {
+  const double t = g_wait_limit_s.load() * (double)d.wall_khz * 1e3;
+  return t >= 9.0e18 ? (long long)9e18 : (long long)t;
+}
 
 constexpr int kMaxDev = 64;
 std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
@@ -891,6 +923,8 @@ DevInfo dev_info() {
     TT_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     TT_REQUIRE(coop != 0, "device does not support cooperative launches");
     TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    TT_HIP(hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, dev));
+    TT_REQUIRE(d.wall_khz > 0, "device reports no wall-clock rate");
     for (int v = 0; v < 4; ++v)
       TT_HIP(hipFuncSetAttribute(kernel_ptr(v >= 2, (v & 1) != 0),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
@@ -1060,6 +1094,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.tol = tol;
   a.eta = eta;
   a.inner_tol = inner_tol;
+  a.wait_limit = wait_limit_ticks(di);
   a.info = info;
   TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
 
@@ -1073,7 +1108,8 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
     to_f32_kernel<<<(int)std::min<int64_t>(1024, (nr + 255) / 256), 256, 0, s>>>(phiR, r32, nr);
     TT_HIP(hipGetLastError());
   }
-  fill(s, barslot, 17, 0.0);
+  fill(s, barslot, 32, 0.0);   // count, epoch flag, abort word
+  fill(s, info + 4, 1, 0.0);
   ++g_launches;
   hipEvent_t pe = nullptr;
   if (g_probe) pe = g_probe->begin(s, kProbeKrylov, 0.0, 0.0);   // work amended after the run
@@ -1086,6 +1122,8 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   if (pe) g_probe->end(s);
   return pe != nullptr;
 }
+
+void krylov_set_wait_limit(double seconds) { g_wait_limit_s.store(seconds); }
 
 int krylov_restart(const KrylovShape& sh, int restart, bool mixed) {
   const Plan p = make_plan(sh, restart, dev_info().lds_max, mixed);

@@ -60,7 +60,7 @@ struct Solver {
   void* hostmem = nullptr;
   double* h_res = nullptr;    // d local residuals
   double* h_k = nullptr;      // k, k_prev
-  double* h_kry = nullptr;    // 3 per core: persistent GMRES [iterations, converged, res]
+  double* h_kry = nullptr;    // 5 per core: persistent GMRES [iterations, converged, res, -, gave up]
   HostBuf hb{nullptr, nullptr};
   std::vector<char> kry_pending;
   std::vector<int> kry_slot;

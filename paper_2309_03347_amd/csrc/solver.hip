@@ -324,11 +324,11 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   mem_bytes = dry.used + 4096;
   TT_HIP(hipMalloc(&mem, mem_bytes));
   TT_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
-  TT_HIP(hipHostMalloc(&hostmem, (size_t)(4 * d + 32) * sizeof(double), hipHostMallocDefault));
+  TT_HIP(hipHostMalloc(&hostmem, (size_t)(6 * d + 32) * sizeof(double), hipHostMallocDefault));
   h_res = static_cast<double*>(hostmem);
   h_k = h_res + d;
   h_kry = h_k + 2;
-  hb.d = h_kry + 3 * d;
+  hb.d = h_kry + 5 * d;
   hb.i = reinterpret_cast<int*>(hb.d + 8);
   kry_pending.assign(d, 0);
   kry_slot.assign(d, -1);
@@ -429,7 +429,7 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   // solves only need to reduce their residual by a fixed factor.
   LocalSolveOpts lo = lso;
   if (cap_bound) lo.eta = cap_eta;
-  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lo, lw, false, h_kry + 3 * k);
+  LocalSolveResult lr = local_solve(s, xh, fvec, xloc, lo, lw, false, h_kry + 5 * k);
   if (lr.deferred) {
     // iterations are read at the end of the sweep
     kry_pending[k] = 1;
@@ -589,7 +589,8 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
     for (int k = 0; k < d; ++k) max_res = std::max(max_res, h_res[k]);
     for (int k = 0; k < d; ++k) {
       if (!kry_pending[k]) continue;
-      const int it = (int)h_kry[3 * k];
+      if (h_kry[5 * k + 4] != 0.0) throw_barrier_abort();
+      const int it = (int)h_kry[5 * k];
       st.local_iters += it;
       krylov_probe_amend(kry_op[k], lso.restart, it, kry_slot[k], kry_mixed[k] != 0);
       kry_pending[k] = 0;

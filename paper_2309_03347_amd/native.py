@@ -24,7 +24,8 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_dot_workspace", "tt_dot", "tt_local_solve_workspace", "tt_local_solve",
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
-            "tt_solver_probe_stats", "tt_power_step_batched"]
+            "tt_solver_probe_stats", "tt_power_step_batched",
+            "ttnt_set_grid_wait_limit"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -129,6 +130,7 @@ def lib():
         L.tt_local_solve_workspace.restype = ctypes.c_size_t
         L.tt_local_solve.argtypes = [ctypes.POINTER(TTLocal), v, ctypes.POINTER(TTSolveOpts),
                                      ctypes.POINTER(TTSolveInfo), v, ctypes.c_size_t, v]
+        L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
@@ -303,6 +305,11 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
     torch.cuda.synchronize()
     return x, dict(iterations=info.iterations, method=info.method_used, rel_res=info.rel_res,
                    converged=st == TT_OK)
+
+
+def set_grid_wait_limit(seconds: float) -> None:
+    """Seconds a persistent solve's workgroup waits at a grid barrier (default 20)."""
+    _check(lib().ttnt_set_grid_wait_limit(ctypes.c_double(seconds)))
 
 
 def _info_dict(info) -> dict:

@@ -143,3 +143,4 @@ def test_batched_step_validates_arguments():
     twice = (ctypes.c_void_p * 2)(0x1000, 0x1000)     # never dereferenced: rejected first
     assert lib.tt_power_step_batched(twice, 2, infos, streams, 1) == native.TT_E_ARG
     assert b"twice" in lib.tt_last_error()
+

@@ -110,3 +110,59 @@ def test_persistent_gmres_iteration_limit(cuda):
     r = M @ x.cpu().numpy().reshape(-1) - f
     assert np.linalg.norm(r) < 0.9 * np.linalg.norm(f)
     assert abs(info["rel_res"] - np.linalg.norm(r) / np.linalg.norm(f)) <= 1e-10
+
+
+# Shapes of the 32^3 four-group workload and beyond: R_H r_1 >= 2016, so the
+# PhiR stream runs its double-buffered full-block loop.  The explicit local
+# matrix would be too large, so the checker applies the operator factored.
+LARGE = [
+    # ra, RL, n, RR, rc, restart
+    (36, 56, 2, 56, 36, 80),     # the bench's rank-36 cores (matrix-core first product)
+    (64, 24, 2, 72, 64, 60),     # n r0 = 128: vector-FMA first product, 8192 unknowns
+]
+
+
+@pytest.mark.parametrize("ra,RL,n,RR,rc,restart", LARGE)
+def test_persistent_gmres_bench_shapes(cuda, ra, RL, n, RR, rc, restart):
+    from paper_2309_03347_amd import native
+    rng = np.random.default_rng(7 * ra + rc)
+    phiL, A, phiR, f = _system(rng, ra, RL, n, RR, rc)
+    shape = (ra, n, rc)
+    out = {}
+    for method, precision in ((2, 0), (4, 0), (2, 1)):
+        print(f"local solve method={method} precision={precision} shape={(ra, RL, n, RR, rc)}",
+              flush=True)
+        x, info = native.tt_local_solve(_t(phiL), _t(A), _t(phiR), _t(f.reshape(shape)),
+                                        _t(np.zeros(shape)), method=method, tol=1e-12,
+                                        max_iter=3000, restart=restart, direct_max=0,
+                                        precision=precision)
+        x = x.cpu().numpy().reshape(-1)
+        assert info["method"] == method and info["converged"], info
+        r = OT.local_apply(phiL, A, phiR, x) - f
+        assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(f), info
+        out[(method, precision)] = x
+    assert np.linalg.norm(out[(2, 0)] - out[(4, 0)]) <= 1e-9 * np.linalg.norm(out[(4, 0)])
+
+
+def test_grid_barrier_wait_gives_up_with_an_error(cuda):
+    # A limit <= 0 makes every workgroup that has to wait give up at once: the
+    # solve must end (every workgroup exits) and report TT_E_HIP.  The wait is
+    # forced from the host; no workgroup is ever left unable to proceed.
+    from paper_2309_03347_amd import native
+    rng = np.random.default_rng(11)
+    ra, RL, n, RR, rc = 36, 6, 2, 8, 36
+    phiL, A, phiR, f = _system(rng, ra, RL, n, RR, rc)
+    shape = (ra, n, rc)
+    args = (_t(phiL), _t(A), _t(phiR), _t(f.reshape(shape)), _t(np.zeros(shape)))
+    native.set_grid_wait_limit(-1.0)
+    try:
+        with pytest.raises(native.TTError) as e:
+            native.tt_local_solve(*args, method=2, tol=1e-12, max_iter=200, restart=40)
+        assert e.value.status == native.TT_E_HIP
+        assert "gave up" in str(e.value)
+    finally:
+        native.set_grid_wait_limit(20.0)
+    x, info = native.tt_local_solve(*args, method=2, tol=1e-12, max_iter=2000, restart=40)
+    assert info["converged"]
+    r = OT.local_apply(phiL, A, phiR, x.cpu().numpy().reshape(-1)) - f
+    assert np.linalg.norm(r) <= 1e-11 * np.linalg.norm(f)

@@ -107,3 +107,13 @@ def test_dot_of_rank_one_trains_is_product_of_factor_dots():
     ref = np.prod([x @ y for x, y in zip(a, b)])
     got = OT.dot([v.reshape(1, -1, 1) for v in a], [v.reshape(1, -1, 1) for v in b])
     assert abs(got - ref) < 1e-13 * max(1.0, abs(ref))
+
+
+def test_local_apply_equals_local_matrix():
+    rng = np.random.default_rng(7)
+    phiL = rng.standard_normal((3, 4, 3))
+    A = rng.standard_normal((4, 3, 3, 2))
+    phiR = rng.standard_normal((5, 2, 5))
+    x = rng.standard_normal(3 * 3 * 5)
+    ref = OT.local_matrix(phiL, A, phiR) @ x
+    assert np.allclose(OT.local_apply(phiL, A, phiR, x), ref, rtol=1e-13, atol=1e-13)
