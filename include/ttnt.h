@@ -166,6 +166,21 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts);
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
                          tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream);
 
+/*
+ * tt_local_solve_noalloc - tt_local_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same system, options, results and errors as
+ * tt_local_solve, but the workspace is a static device array of 64 MiB that
+ * the library holds on each GPU it runs on until the process ends; nothing is
+ * allocated by the call (no hipMalloc, hipFree or allocating library
+ * routine).  A system whose tt_local_solve_workspace exceeds 64 MiB returns
+ * TT_E_CAPACITY with nothing written.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams or threads)
+ * race, so the caller serializes them.  The caller still owns sys's buffers
+ * and x.  Synchronizes `stream`.
+ */
+tt_status tt_local_solve_noalloc(const tt_local* sys, double* x, const tt_solve_opts* opts,
+                                 tt_solve_info* info, tt_stream stream);
 
 /*
  * ttnt_set_grid_wait_limit - how long (seconds, default 20) a workgroup of a

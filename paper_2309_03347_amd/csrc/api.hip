@@ -133,6 +133,29 @@ void local_solve_impl(const tt_local* sys, double* x, const tt_solve_opts* opts,
   if (!r.converged) throw NoConvError{};
 }
 
+// Static scratch of the allocation-free local solve.  Each device holds its
+// own copy for the life of the process; its address there is looked up once
+// per device (the array's name is not a device address in host code).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+void* noalloc_scratch() {
+  constexpr int kMaxDev = 64;
+  static void* ptr[kMaxDev] = {};
+  static std::mutex mu;
+  int dev = 0;
+  TT_HIP(hipGetDevice(&dev));
+  TT_REQUIRE(dev >= 0 && dev < kMaxDev, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    TT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TT_REQUIRE(p != nullptr, "static scratch has no device address");
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -236,6 +259,20 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts) 
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
                          tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream) {
   return guard([&] { local_solve_impl(sys, x, opts, info, ws, ws_bytes, (hipStream_t)stream); });
+}
+
+tt_status tt_local_solve_noalloc(const tt_local* sys, double* x, const tt_solve_opts* opts,
+                                 tt_solve_info* info, tt_stream stream) {
+  return guard([&] {
+    TT_REQUIRE(sys != nullptr, "NULL system");
+    const size_t need = tt_local_solve_workspace(sys, opts);
+    if (need > kNoAllocScratchBytes)
+      throw CapacityError{"system needs " + std::to_string(need) +
+                          " bytes of workspace, above the static scratch of " +
+                          std::to_string(kNoAllocScratchBytes)};
+    local_solve_impl(sys, x, opts, info, noalloc_scratch(), kNoAllocScratchBytes,
+                     (hipStream_t)stream);
+  });
 }
 
 tt_status ttnt_set_grid_wait_limit(double seconds) {

@@ -24,7 +24,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_dot_workspace", "tt_dot", "tt_local_solve_workspace", "tt_local_solve",
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
-            "tt_solver_probe_stats", "tt_power_step_batched",
+            "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit"]
 
 
@@ -130,6 +130,9 @@ def lib():
         L.tt_local_solve_workspace.restype = ctypes.c_size_t
         L.tt_local_solve.argtypes = [ctypes.POINTER(TTLocal), v, ctypes.POINTER(TTSolveOpts),
                                      ctypes.POINTER(TTSolveInfo), v, ctypes.c_size_t, v]
+        L.tt_local_solve_noalloc.argtypes = [ctypes.POINTER(TTLocal), v,
+                                             ctypes.POINTER(TTSolveOpts),
+                                             ctypes.POINTER(TTSolveInfo), v]
         L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
@@ -301,6 +304,27 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
     st = lib().tt_local_solve(ctypes.byref(sysd), ctypes.c_void_p(x.data_ptr()), ctypes.byref(opts),
                               ctypes.byref(info), ctypes.c_void_p(ws.data_ptr()),
                               ctypes.c_size_t(ws.numel() * 8), _stream())
+    _check(st, allow=(TT_E_NOCONV,))
+    torch.cuda.synchronize()
+    return x, dict(iterations=info.iterations, method=info.method_used, rel_res=info.rel_res,
+                   converged=st == TT_OK)
+
+
+def tt_local_solve_noalloc(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
+                           max_iter: int = 1000, restart: int = 80, direct_max: int = 256,
+                           precision: int = 0):
+    """tt_local_solve on the library's static scratch (no workspace argument)."""
+    torch = _torch()
+    ra, RL, _ = phiL.shape
+    RL2, m, n, RR = A.shape
+    rc = phiR.shape[0]
+    tensors = [t.contiguous() for t in (phiL, A, phiR, f)]
+    x = x0.contiguous().clone()
+    sysd = TTLocal(ra, RL, m, n, RR, rc, *[ctypes.c_void_p(t.data_ptr()) for t in tensors])
+    opts = TTSolveOpts(method, tol, max_iter, restart, direct_max, precision)
+    info = TTSolveInfo()
+    st = lib().tt_local_solve_noalloc(ctypes.byref(sysd), ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.byref(opts), ctypes.byref(info), _stream())
     _check(st, allow=(TT_E_NOCONV,))
     torch.cuda.synchronize()
     return x, dict(iterations=info.iterations, method=info.method_used, rel_res=info.rel_res,

@@ -144,3 +144,16 @@ def test_batched_step_validates_arguments():
     assert lib.tt_power_step_batched(twice, 2, infos, streams, 1) == native.TT_E_ARG
     assert b"twice" in lib.tt_last_error()
 
+
+def test_noalloc_local_solve_rejects_systems_above_its_scratch():
+    # 64 MiB of static scratch: a 2 x 300 x 300 dense system needs far more
+    # workspace, so the call fails before touching the device.
+    lib = native.lib()
+    fake = ctypes.c_void_p(0x1000)
+    sysd = native.TTLocal(300, 4, 2, 2, 4, 300, fake, fake, fake, fake)
+    opts = native.TTSolveOpts(1, 1e-12, 100, 40, 1 << 30, 0)
+    info = native.TTSolveInfo()
+    st = lib.tt_local_solve_noalloc(ctypes.byref(sysd), fake, ctypes.byref(opts),
+                                    ctypes.byref(info), None)
+    assert st == native.TT_E_CAPACITY
+    assert b"static scratch" in lib.tt_last_error()
