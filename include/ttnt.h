@@ -109,6 +109,17 @@ tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* w
                    size_t ws_bytes, tt_stream stream);
 
 /*
+ * tt_orth_right - in-place right orthogonalization: a right-to-left sweep of
+ * QR factorizations of the transposed unfoldings makes cores 1..d-1
+ * right-orthonormal (each core's rows orthonormal over (n_k, r_{k+1})),
+ * with the R factors pushed into core k-1; the tensor is unchanged (the
+ * orthogonalization step of TT rounding, Section 2.2).  Ranks may shrink to
+ * min(r_k, n_k r_{k+1}); x->r is updated.  `ws` at least tt_round_workspace(x)
+ * bytes.  Synchronizes `stream`.
+ */
+tt_status tt_orth_right(tt_vec* x, void* ws, size_t ws_bytes, tt_stream stream);
+
+/*
  * tt_dot - inner product <a, b> of two TT vectors with equal modes
  * (sequential contraction of the core pairs).  result: host double.
  * `ws` device workspace of tt_dot_workspace(a, b) bytes.  Synchronizes.

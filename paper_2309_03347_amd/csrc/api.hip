@@ -217,6 +217,21 @@ tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* w
   });
 }
 
+tt_status tt_orth_right(tt_vec* x, void* ws, size_t ws_bytes, tt_stream stream) {
+  return guard([&] {
+    check_vec(x, "x");
+    TT_REQUIRE(ws != nullptr, "workspace is NULL");
+    TTv t = view(x);
+    if (ws_bytes < round_ws_bytes(t)) throw CapacityError{"workspace smaller than tt_round_workspace"};
+    Bump b;
+    b.base = (char*)ws;
+    b.cap = ws_bytes;
+    orth_right((hipStream_t)stream, t, b);
+    TT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];
+  });
+}
+
 size_t tt_dot_workspace(const tt_vec* a, const tt_vec* b) {
   if (!a || !b || a->d < 1 || a->d != b->d) return 0;
   TTv ta, tb;

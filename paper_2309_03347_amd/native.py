@@ -25,7 +25,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
-            "ttnt_set_grid_wait_limit"]
+            "ttnt_set_grid_wait_limit", "tt_orth_right"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -134,6 +134,7 @@ def lib():
                                              ctypes.POINTER(TTSolveOpts),
                                              ctypes.POINTER(TTSolveInfo), v]
         L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
+        L.tt_orth_right.argtypes = [ctypes.POINTER(TTVec), v, ctypes.c_size_t, v]
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
@@ -270,6 +271,15 @@ def tt_round(x: DeviceTT, tol: float, rmax: int) -> float:
                           ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * 8),
                           _stream()))
     return err.value
+
+
+def tt_orth_right(x: DeviceTT) -> None:
+    """In-place right orthogonalization of cores 1..d-1 (ranks may shrink)."""
+    xd = x.desc()
+    nbytes = lib().tt_round_workspace(ctypes.byref(xd))
+    ws = _workspace(nbytes)
+    _check(lib().tt_orth_right(ctypes.byref(xd), ctypes.c_void_p(ws.data_ptr()),
+                               ctypes.c_size_t(ws.numel() * 8), _stream()))
 
 
 def tt_dot(a: DeviceTT, b: DeviceTT) -> float:

@@ -67,6 +67,25 @@ def _interp(l, pos, no_bc=False):
     return qtt.tt_sum([base, qtt.qtt_corner(l, pos, -0.5)])
 
 
+def _diff_nobc(l, h, pos):
+    # D^+ without its inflow row (row 0, entry 1/h); D^- without row n-1 (-1/h)
+    return qtt.tt_sum([_diff(l, h, pos), qtt.qtt_corner(l, pos, -1.0 / h if pos else 1.0 / h)])
+
+
+def _row_projector(l, pos):
+    # I minus the inflow-row selector e_in e_in^T
+    return qtt.tt_sum([qtt.qtt_eye(l), qtt.qtt_corner(l, pos, -1.0)])
+
+
+def _face_rows(l, h, pos, periodic):
+    """(1/h) e_in (e_in - e_out)^T for a periodic axis, (1/h) e_in e_in^T for a
+    vacuum one; e_in is node 0 for a positive cosine, node n-1 otherwise."""
+    rows = qtt.qtt_corner(l, pos, 1.0 / h)
+    if not periodic:
+        return rows
+    return qtt.tt_sum([rows, qtt.qtt_outer(l, pos, not pos, -1.0 / h)])
+
+
 def _row_intervals(wl, ax, pos):
     """Node-row interval of every block along axis ``ax`` for one octant sign.
 
@@ -93,17 +112,19 @@ def _coef_tt(coef: np.ndarray):
     return e, cores[1], cores[2], cores[3][:, :, 0]
 
 
-def _material_term(wl, o, energy_mats: np.ndarray, no_bc: bool) -> Cores:
+def _material_term(wl, o, energy_mats: np.ndarray, no_bc: bool,
+                   collision: bool = False) -> Cores:
     """sum_blocks E[mat(b)] (x) angle (x) R_z P_z (x) R_y P_y (x) R_x P_x.
 
     ``energy_mats[m]`` is the G x G energy factor of material m; the angle
-    factor is C_o (x) I for H (no_bc False) or Intg^o for S, F (no_bc True).
+    factor is C_o (x) I for H (no_bc False, or ``collision``) or Intg^o for
+    S, F (no_bc True).
     """
     G, L, l = wl.G, wl.L, wl.l
     per = L // 8
     sel = np.zeros(L)
     sel[o * per:(o + 1) * per] = 1.0
-    angle = np.outer(sel, wl.quad.w) if no_bc else np.diag(sel)
+    angle = np.outer(sel, wl.quad.w) if (no_bc and not collision) else np.diag(sel)
     Bz, By, Bx = wl.block_mat.shape
     coef = np.zeros((G * G, Bz, By, Bx))
     for bz in range(Bz):
@@ -160,6 +181,39 @@ def octant_terms(wl, o):
     return terms
 
 
+def octant_terms_explicit_faces(wl, o):
+    """Octant o's rows of H with explicit face rows (used when an axis is periodic).
+
+    The cell rows are the terms of ``octant_terms`` with every 1D factor's
+    inflow row removed (so they vanish on the inflow faces).  Each inflow-face
+    node then gets one row, taken from the x face first, then y, then z:
+    psi(node) - psi(opposite node) = 0 on a periodic axis, psi(node) = 0 on a
+    vacuum one (both scaled by 1/h).  For vacuum axes this has the same
+    solutions as ``octant_terms``, whose face rows are a two-dimensional
+    transport problem with no source.
+    """
+    l, h = wl.l, 1.0 / (wl.n - 1)
+    px, py, pz = _octant_signs(o)
+    per_z, per_y, per_x = (bool(p) for p in wl.periodic)
+    per = wl.L // 8
+    sel = np.zeros(wl.L)
+    sel[o * per:(o + 1) * per] = 1.0
+    q = wl.quad
+    Ix, Iy, Iz = (_interp(l, p, True) for p in (px, py, pz))
+    Dx, Dy, Dz = (_diff_nobc(l, h, p) for p in (px, py, pz))
+    Px, Py = _row_projector(l, px), _row_projector(l, py)
+    E = qtt.qtt_eye(l)
+    return [
+        qtt.kron_chain([_energy_angle(wl, sel * q.mu), Iz, Iy, Dx]),
+        qtt.kron_chain([_energy_angle(wl, sel * q.eta), Iz, Dy, Ix]),
+        qtt.kron_chain([_energy_angle(wl, sel * q.xi), Dz, Iy, Ix]),
+        _material_term(wl, o, np.stack([np.diag(s) for s in wl.sigma_t]), True, collision=True),
+        qtt.kron_chain([_energy_angle(wl, sel), E, E, _face_rows(l, h, px, per_x)]),
+        qtt.kron_chain([_energy_angle(wl, sel), E, _face_rows(l, h, py, per_y), Px]),
+        qtt.kron_chain([_energy_angle(wl, sel), _face_rows(l, h, pz, per_z), Py, Px]),
+    ]
+
+
 def _round(cores, tol):
     return qtt.tt_round_host(cores, tol)
 
@@ -171,8 +225,10 @@ def build(wl, tol: float = 1e-13) -> Operators:
     F = None
     Es = np.asarray(wl.sigma_s)
     Ef = np.einsum("g,mh->mgh", wl.chi, wl.nu_sigma_f)
+    explicit = any(getattr(wl, "periodic", (False, False, False)))
     for o in range(8):
-        Ho = _round(qtt.tt_sum(octant_terms(wl, o)), tol)
+        terms = octant_terms_explicit_faces(wl, o) if explicit else octant_terms(wl, o)
+        Ho = _round(qtt.tt_sum(terms), tol)
         H = Ho if H is None else _round(qtt.tt_sum([H, Ho]), tol)
         So = _round(_material_term(wl, o, Es, True), tol)
         S = So if S is None else _round(qtt.tt_sum([S, So]), tol)
@@ -196,8 +252,9 @@ def build_unrounded(wl):
     Es = np.asarray(wl.sigma_s)
     Ef = np.einsum("g,mh->mgh", wl.chi, wl.nu_sigma_f)
     Ht, St, Ft = [], [], []
+    explicit = any(getattr(wl, "periodic", (False, False, False)))
     for o in range(8):
-        Ht += octant_terms(wl, o)
+        Ht += octant_terms_explicit_faces(wl, o) if explicit else octant_terms(wl, o)
         St.append(_material_term(wl, o, Es, True))
         Ft.append(_material_term(wl, o, Ef, True))
     return qtt.tt_sum(Ht), qtt.tt_sum(St), qtt.tt_sum(Ft)

@@ -92,6 +92,19 @@ def qtt_corner(l: int, first: bool, value: float) -> Cores:
     return cores
 
 
+def qtt_outer(l: int, row_first: bool, col_first: bool, value: float) -> Cores:
+    """``value * e_a e_b^T`` for e_a, e_b each the first (node 0) or last
+    (node n-1) basis vector: one nonzero per bit core (rank 1)."""
+    a = 0 if row_first else 1
+    b = 0 if col_first else 1
+    cores = []
+    for t in range(l):
+        c = np.zeros((1, 2, 2, 1))
+        c[0, a, b, 0] = value if t == 0 else 1.0
+        cores.append(c)
+    return cores
+
+
 def qtt_interval(l: int, lo: int, hi: int) -> Cores:
     """QTT vector (cores [r, 2, r']) of the indicator of lo <= i <= hi.
 

@@ -109,11 +109,15 @@ class Workload:
 
 
 def level_symmetric(N: int) -> Quadrature:
-    """LQn point set of order N in the paper's octant order, uniform weights.
+    """LQn point set of order N in the paper's octant order, with LQn weights.
 
-    Weights are all 1/L (sum 1, octant-symmetric, so odd moments vanish and the
-    second moments are 1/3); the quadrature is an input shared by every
-    consumer, so parity does not depend on which weights are used.
+    The points of one octant fall into classes (the multiset of their three
+    cosine indices); every point of a class gets the same weight, and the
+    class weights make the set integrate mu^(2m) exactly for m < N/2 (the
+    even-moment conditions that define the level-symmetric weights; they
+    reproduce the published LQn values, e.g. 0.1209877, 0.0907407 and
+    0.0925926 for S8 with the octant normalized to 1).  Weights sum to 1 over
+    all L directions.
     """
     if N not in _LQN_MU1:
         raise ValueError(f"no level-symmetric set for S{N}")
@@ -125,18 +129,28 @@ def level_symmetric(N: int) -> Quadrature:
         delta = 2.0 * (1.0 - 3.0 * mu1 * mu1) / (N - 2)
         cos = np.sqrt(mu1 * mu1 + delta * np.arange(h))
     trip = []
+    cls = []
     for i in range(1, h + 1):
         for j in range(1, h + 1):
             k = h + 2 - i - j
             if 1 <= k <= h:
                 v = np.array([cos[i - 1], cos[j - 1], cos[k - 1]])
                 trip.append(v / np.linalg.norm(v))
+                cls.append(tuple(sorted((i, j, k))))
     trip = np.array(trip)
+    keys = sorted(set(cls))
+    member = np.array([[1.0 if c == key else 0.0 for key in keys] for c in cls])
+    moments = np.array([[(trip[member[:, q] > 0, 0] ** (2 * m)).sum() for q in range(len(keys))]
+                        for m in range(h)])
+    target = 1.0 / (2.0 * np.arange(h) + 1.0)
+    wc = np.linalg.lstsq(moments, target, rcond=None)[0]
+    w_oct = member @ wc                     # per point, octant sum 1
     per = trip.shape[0]
     L = 8 * per
     mu = np.empty(L)
     eta = np.empty(L)
     xi = np.empty(L)
+    w = np.empty(L)
     for o in range(8):
         sx = 1.0 if (o & 1) else -1.0
         sy = 1.0 if (o & 2) else -1.0
@@ -145,7 +159,8 @@ def level_symmetric(N: int) -> Quadrature:
         mu[sl] = sx * trip[:, 0]
         eta[sl] = sy * trip[:, 1]
         xi[sl] = sz * trip[:, 2]
-    return Quadrature(mu, eta, xi, np.full(L, 1.0 / L))
+        w[sl] = w_oct / 8.0
+    return Quadrature(mu, eta, xi, w)
 
 
 def _draw_materials(rng, n_mat: int, G: int, upscatter_groups: int = 0):

@@ -52,3 +52,33 @@ def test_batched_steps_match_single_instance_steps(cuda, nstreams):
         assert all(np.array_equal(x, y) for x, y in zip(pb, pa)), i
     for s in batch + alone:
         s.close()
+
+
+def test_batched_steps_match_the_oracle_per_instance(cuda):
+    # Every instance of a batch against the checker's exact step from the same
+    # (densified) iterate, with the rank caps lifted so that the truncation
+    # tolerance governs: k to 1e-8 relative, flux to 1e-6 (FP64 bar).
+    import torch
+    from oracle import sweep, tt as OT
+    wls = [W.inner_box(l=2, G=1, N=2, seed=1100, rmax=256, tol=1e-10),
+           W.inner_box(l=3, G=1, N=2, seed=1101, rmax=256, tol=1e-10),
+           W.inner_box(l=2, G=2, N=4, seed=1102, rmax=256, tol=1e-10),
+           W.homogeneous(l=3, N=4, seed=1103, rmax=256, tol=1e-10),
+           W.inner_box(l=2, G=3, N=2, seed=1104, rmax=256, tol=1e-10)]
+    batch = [KeffSolver(w, kick=8, max_sweeps=60) for w in wls]
+    probs = [sweep.Problem.from_workload(w) for w in wls]
+    psis = [OT.full_vec(s.native.psi().cores()) for s in batch]
+    ks = [1.0] * len(batch)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    unit = lambda v: (v / np.linalg.norm(v)) * (1 if v.sum() >= 0 else -1)
+    for step in range(3):
+        print(f"batched oracle step {step}", flush=True)
+        recs = step_batched(batch, streams)
+        for i, (s, p) in enumerate(zip(batch, probs)):
+            ref, kref = p.power_step(psis[i], ks[i])
+            got = OT.full_vec(s.psi_cores())
+            assert abs(recs[i].k - kref) <= 1e-8 * abs(kref), (i, step, recs[i].k, kref)
+            assert np.linalg.norm(unit(got) - unit(ref)) <= 1e-6, (i, step)
+            psis[i], ks[i] = got, recs[i].k
+    for s in batch:
+        s.close()

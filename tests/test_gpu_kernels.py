@@ -52,6 +52,12 @@ def _inflate(rng, x):
     ((8,) + (2,) * 9, (6, 9, 12, 14, 12, 9, 6, 4, 2)),
     # inflated ranks up to 66: SVDs with 4 lanes per Jacobi pair
     ((4,) * 6, (3, 9, 22, 9, 3)),
+    # an angle-like core of 80 directions between rank 8 and rank 64 (192
+    # inflated): QR of 640 x 192 and 3072 x 24 and SVDs of 5120 x 8 and
+    # 192 x 128 outside LDS (global-memory factorizations)
+    ((8, 80, 16, 8), (8, 64, 8)),
+    # rank 140 (420 inflated): SVD of 144 x 144, more than 128 columns
+    ((12, 12, 12, 12), (12, 140, 12)),
 ])
 def test_round_recovers_exact_ranks(cuda, modes, ranks):
     from paper_2309_03347_amd import native
@@ -113,6 +119,21 @@ def test_round_rank_cap_binds(cuda):
     assert np.linalg.norm(y - full) >= best * (1 - 1e-10)
 
 
+def test_orth_right_keeps_the_tensor(cuda):
+    from paper_2309_03347_amd import native
+    rng = np.random.default_rng(12)
+    modes = (8, 80, 16, 8)
+    x = _rand_tt(rng, modes, (8, 64, 8))
+    full = OT.full_vec(x)
+    d = native.DeviceTT.from_cores(x)
+    native.tt_orth_right(d)
+    y = d.cores()
+    assert np.linalg.norm(OT.full_vec(y) - full) <= 1e-12 * np.linalg.norm(full)
+    for k in range(1, len(modes)):
+        c = y[k].reshape(y[k].shape[0], -1)
+        assert np.allclose(c @ c.T, np.eye(c.shape[0]), atol=1e-12), k
+
+
 def test_dot_matches_dense(cuda):
     from paper_2309_03347_amd import native
     rng = np.random.default_rng(9)
@@ -158,6 +179,7 @@ def _local_system(rng, ra, RL, n, RR, rc, shift=8.0):
     (3, 4, 3, 3, 3, 36),     # blocks of 144, as at the angle core of the 32^3 case
     (3, 6, 3, 3, 3, 32),     # blocks of 192
     (3, 5, 3, 3, 3, 40),     # blocks of 200: LU in global memory
+    (3, 8, 3, 6, 3, 68),     # blocks of 544 (rank 8 | rank 64 + kick): LU outside LDS
 ])
 def test_local_solve_matches_dense(cuda, method, ra, RL, n, RR, rc):
     from paper_2309_03347_amd import native

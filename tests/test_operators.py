@@ -89,3 +89,48 @@ def test_initial_flux_matches_dense_start():
     wl = W.inner_box(l=2, G=2, N=4, seed=8)
     ops = O.build(wl)
     assert np.allclose(OT.full_vec(ops.psi0), sweep.dense_psi0(wl))
+
+
+@pytest.mark.parametrize("N", [2, 4, 6, 8, 16])
+def test_level_symmetric_moments(N):
+    # the quadrature integrates the even moments of each cosine over the
+    # unit sphere (mean of mu^2m = 1/(2m+1)) up to m = N/2 - 1, odd moments
+    # vanish, and all weights are positive
+    from paper_2309_03347_amd import workload as W
+    q = W.level_symmetric(N)
+    assert q.L == {2: 8, 4: 24, 6: 48, 8: 80, 16: 288}[N]
+    assert np.all(q.w > 0) and abs(q.w.sum() - 1) < 1e-14
+    for c in (q.mu, q.eta, q.xi):
+        assert abs((q.w * c).sum()) < 1e-15
+        for m in range(N // 2):
+            assert abs((q.w * c ** (2 * m)).sum() - 1 / (2 * m + 1)) < 1e-13
+    assert np.allclose(q.mu ** 2 + q.eta ** 2 + q.xi ** 2, 1.0, atol=1e-14)
+
+
+def test_level_symmetric_s8_weights_are_the_published_ones():
+    from paper_2309_03347_amd import workload as W
+    q = W.level_symmetric(8)
+    per = q.L // 8
+    w = np.sort(np.unique(np.round(q.w[:per] * 8, 7)))
+    assert np.allclose(w, [0.0907407, 0.0925926, 0.1209877], atol=2e-7)
+
+
+@pytest.mark.parametrize("per", [(True, True, True), (False, True, False)])
+@pytest.mark.parametrize("maker", [lambda: W.homogeneous(l=2, N=2, seed=3),
+                                   lambda: W.inner_box(l=2, G=2, N=4, seed=5)])
+def test_periodic_operators_equal_dense_rows(maker, per):
+    # explicit face rows: cell rows equal the equation rows, each inflow-face
+    # row is the checker's periodic (or vacuum) face row scaled by 1/h; S and
+    # F are unchanged
+    wl = maker()
+    wl.periodic = per
+    ops = O.build(wl)
+    H, S, F = (m.toarray() for m in dense.equation_operators(wl))
+    Ht = OT.full_mat(ops.H)
+    idx = dense.cell_row_index(wl)
+    face = np.setdiff1d(np.arange(H.shape[0]), idx)
+    h = 1.0 / (wl.n - 1)
+    assert np.abs(Ht[idx] - H[idx]).max() < 1e-12 * np.abs(H).max()
+    assert np.abs(Ht[face] - H[face] / h).max() < 1e-12 / h
+    assert np.abs(OT.full_mat(ops.S) - S).max() < 1e-14
+    assert np.abs(OT.full_mat(ops.F) - F).max() < 1e-14
