@@ -218,6 +218,41 @@ def _round(cores, tol):
     return qtt.tt_round_host(cores, tol)
 
 
+# The angle factor of every term is diagonal in H (C_o (x) I, Q_mu^o, ...) and
+# of the form a (x) w^T in S and F (Intg^o = sel_o w^T, the same w for every
+# octant).  Rounding sums of such terms with the L x L angle mode stored in
+# full would factor L^2-long unfoldings; the compressed forms below carry only
+# the L row entries and are exact, so the rounded operator is the same.
+def _angle_index(wl) -> int:
+    return 1 if wl.G > 1 else 0
+
+
+def _squeeze_angle(cores: Cores, wl, kind: str) -> Cores:
+    k = _angle_index(wl)
+    c = cores[k]
+    if kind == "diag":
+        a = np.einsum("aiib->aib", c)
+        assert np.array_equal(c, np.einsum("aib,ij->aijb", a, np.eye(c.shape[1]))), "angle not diagonal"
+    else:
+        w = wl.quad.w
+        a = c[:, :, 0, :] / w[0]
+        assert np.allclose(c, np.einsum("aib,j->aijb", a, w), rtol=1e-14, atol=0), "angle not a w^T"
+    out = list(cores)
+    out[k] = a[:, :, None, :]
+    return out
+
+
+def _expand_angle(cores: Cores, wl, kind: str) -> Cores:
+    k = _angle_index(wl)
+    a = cores[k][:, :, 0, :]
+    out = list(cores)
+    if kind == "diag":
+        out[k] = np.einsum("aib,ij->aijb", a, np.eye(a.shape[1]))
+    else:
+        out[k] = np.einsum("aib,j->aijb", a, wl.quad.w)
+    return out
+
+
 def build(wl, tol: float = 1e-13) -> Operators:
     """Assemble H, S, F (each summed over octants and compressed exactly)."""
     H = None
@@ -228,12 +263,15 @@ def build(wl, tol: float = 1e-13) -> Operators:
     explicit = any(getattr(wl, "periodic", (False, False, False)))
     for o in range(8):
         terms = octant_terms_explicit_faces(wl, o) if explicit else octant_terms(wl, o)
-        Ho = _round(qtt.tt_sum(terms), tol)
+        Ho = _round(qtt.tt_sum([_squeeze_angle(t, wl, "diag") for t in terms]), tol)
         H = Ho if H is None else _round(qtt.tt_sum([H, Ho]), tol)
-        So = _round(_material_term(wl, o, Es, True), tol)
+        So = _round(_squeeze_angle(_material_term(wl, o, Es, True), wl, "w"), tol)
         S = So if S is None else _round(qtt.tt_sum([S, So]), tol)
-        Fo = _round(_material_term(wl, o, Ef, True), tol)
+        Fo = _round(_squeeze_angle(_material_term(wl, o, Ef, True), wl, "w"), tol)
         F = Fo if F is None else _round(qtt.tt_sum([F, Fo]), tol)
+    H = _expand_angle(H, wl, "diag")
+    S = _expand_angle(S, wl, "w")
+    F = _expand_angle(F, wl, "w")
     cF = [c.sum(axis=1) for c in F]          # F^T 1: sum over the row mode
     cF = qtt.tt_round_host(cF, tol)
     psi0 = []
