@@ -76,6 +76,19 @@ size_t dot_ws_bytes(const TTv& a, const TTv& b);
 // Right-orthogonalize cores 1..d-1 (R->L LQ sweep).
 void orth_right(hipStream_t s, TTv& x, Bump& ws);
 
+// Structure of an operator core in its mode (row i, column j), used to skip
+// work in contractions.  kind 0: general.  kind 1: diagonal,
+// A[b, i, j, b'] = delta_ij Hd[b, i, b'] (the transport operator on the energy
+// and angle cores).  kind 2: proportional columns, A[b, i, j, b'] =
+// a[b, i, b'] w_j (the angular integral of the scattering and fission terms),
+// with Arp[(i, b'), b] = a[b, i, b'].
+struct ModeForm {
+  int kind = 0;
+  const double* Hd = nullptr;    // kind 1: [RL][n][RR]
+  const double* Arp = nullptr;   // kind 2: [(n RR)][RL]
+  const double* w = nullptr;     // kind 2: [n]
+};
+
 // Local operator application y = alpha * (PhiL (x) A (x) PhiR) v + beta * y.
 struct LocalOp {
   const double* phiL;  // [ra][RL][rb]
@@ -86,6 +99,7 @@ struct LocalOp {
   const double* phiR;  // [rc][RR][rd]
   int rc, rd;
   bool diag = false;   // core is diagonal in the mode (A[b, i, j, b'] = 0 for i != j)
+  ModeForm form{};     // structure used by the contractions (kind 0: none)
 };
 void local_apply(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
                  double beta, double* T1, double* T2);

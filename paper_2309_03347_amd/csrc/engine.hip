@@ -274,12 +274,29 @@ void orth_right(hipStream_t s, TTv& x, Bump& ws) {
 // ---------------------------------------------------------------------------
 void local_apply(hipStream_t s, const LocalOp& o, const double* v, double* y, double alpha,
                  double beta, double* T1, double* T2) {
-  // T1[(a, b), (j, d')] = sum_{b2} PhiL[(a, b), b2] v[b2, (j, d')]
-  gemm(s, false, false, o.ra * o.RL, o.n * o.rd, o.rb, 1.0, o.phiL, o.rb, 0, v, o.n * o.rd, 0,
-       0.0, T1, o.n * o.rd, 0);
-  // T2[a][(i, b'), d'] = sum_{(b, j)} Ap[(i, b'), (b, j)] T1[a][(b, j), d']
-  gemm(s, false, false, o.m * o.RR, o.rd, o.RL * o.n, 1.0, o.Ap, o.RL * o.n, 0, T1, o.rd,
-       (int64_t)o.RL * o.n * o.rd, 0.0, T2, o.rd, (int64_t)o.m * o.RR * o.rd, o.ra);
+  if (o.form.kind == 2) {
+    // proportional columns: the mode of v is summed with w first
+    // u[b2, d'] = sum_j w_j v[b2, j, d'] (held in T2 until T2 is rewritten)
+    mode_contract(s, v, o.rb, o.n, o.rd, o.form.w, T2);
+    // T1[(a, b), d'] = sum_{b2} PhiL[(a, b), b2] u[b2, d']
+    gemm(s, false, false, o.ra * o.RL, o.rd, o.rb, 1.0, o.phiL, o.rb, 0, T2, o.rd, 0, 0.0, T1,
+         o.rd, 0);
+    // T2[a][(i, b'), d'] = sum_b Arp[(i, b'), b] T1[a][b, d']
+    gemm(s, false, false, o.m * o.RR, o.rd, o.RL, 1.0, o.form.Arp, o.RL, 0, T1, o.rd,
+         (int64_t)o.RL * o.rd, 0.0, T2, o.rd, (int64_t)o.m * o.RR * o.rd, o.ra);
+  } else {
+    // T1[(a, b), (j, d')] = sum_{b2} PhiL[(a, b), b2] v[b2, (j, d')]
+    gemm(s, false, false, o.ra * o.RL, o.n * o.rd, o.rb, 1.0, o.phiL, o.rb, 0, v, o.n * o.rd, 0,
+         0.0, T1, o.n * o.rd, 0);
+    if (o.form.kind == 1) {
+      // diagonal in the mode: T2[a][i][b'][d'] = sum_b Hd[b, i, b'] T1[a][b][i][d']
+      mode_mix(s, T1, o.ra, o.RL, o.n, o.rd, o.form.Hd, o.RR, T2);
+    } else {
+      // T2[a][(i, b'), d'] = sum_{(b, j)} Ap[(i, b'), (b, j)] T1[a][(b, j), d']
+      gemm(s, false, false, o.m * o.RR, o.rd, o.RL * o.n, 1.0, o.Ap, o.RL * o.n, 0, T1, o.rd,
+           (int64_t)o.RL * o.n * o.rd, 0.0, T2, o.rd, (int64_t)o.m * o.RR * o.rd, o.ra);
+    }
+  }
   // y[(a, i), c] = sum_{(b', d')} T2[(a, i), (b', d')] PhiR[c, (b', d')]
   gemm(s, false, true, o.ra * o.m, o.rc, o.RR * o.rd, alpha, T2, o.RR * o.rd, 0, o.phiR,
        o.RR * o.rd, 0, beta, y, o.rc, 0);

@@ -29,6 +29,14 @@ struct Solver {
   int min_sweeps = 2;          // sweeps before the stagnation test may stop
   bool cap_bound = false;      // the rank cap bound during the previous sweep
   std::vector<char> Hdiag;
+  // structure of each core in its mode, used by the contractions: H's
+  // mode-diagonal cores (kind 1), S + F/k's cores with proportional columns
+  // (kind 2, the angular integral); the identity operator's are general
+  std::vector<char> sf_rank1;
+  std::vector<int> sf_j0;
+  std::vector<std::vector<double>> sf_w;       // host copies of the column weights
+  std::vector<ModeForm> formH, formSF, formId;
+  std::vector<double*> HdH, ArpSF, wSF;
   int64_t last_launches = 0;
   Probe probe;
 
@@ -84,7 +92,8 @@ struct Solver {
  private:
   void plan(Bump& b);
   Co sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
-                   const std::vector<double*>& ApOp, StepStats& st);
+                   const std::vector<double*>& ApOp, const std::vector<ModeForm>& fOp,
+                   StepStats& st);
 };
 
 

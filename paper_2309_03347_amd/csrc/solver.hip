@@ -23,11 +23,23 @@ int64_t sat_mul(int64_t a, int64_t b) {
 // out[a2, b1, c2] = sum PhiL[a, b, c] Y[a, i, a2] A[b, i, j, b1] X[c, j, c2]
 void iface_left(hipStream_t s, const double* phiL, const double* Y, int ry0, int ry1,
                 const double* Ap, int RL, int m, int n, int RR, const double* X, int rx0,
-                int rx1, double* out, double* T1, double* T2) {
-  gemm(s, false, false, ry0 * RL, n * rx1, rx0, 1.0, phiL, rx0, 0, X, n * rx1, 0, 0.0, T1,
-       n * rx1, 0);
-  gemm(s, false, false, m * RR, rx1, RL * n, 1.0, Ap, RL * n, 0, T1, rx1, (int64_t)RL * n * rx1,
-       0.0, T2, rx1, (int64_t)m * RR * rx1, ry0);
+                int rx1, double* out, double* T1, double* T2, const ModeForm& f = ModeForm{}) {
+  if (f.kind == 2) {
+    // u[c, c2] = sum_j w_j X[c, j, c2]; T1[(a, b), c2] = PhiL u;
+    // T2[a][(i, b1), c2] = sum_b Arp[(i, b1), b] T1[a][b, c2]
+    mode_contract(s, X, rx0, n, rx1, f.w, T2);
+    gemm(s, false, false, ry0 * RL, rx1, rx0, 1.0, phiL, rx0, 0, T2, rx1, 0, 0.0, T1, rx1, 0);
+    gemm(s, false, false, m * RR, rx1, RL, 1.0, f.Arp, RL, 0, T1, rx1, (int64_t)RL * rx1, 0.0, T2,
+         rx1, (int64_t)m * RR * rx1, ry0);
+  } else {
+    gemm(s, false, false, ry0 * RL, n * rx1, rx0, 1.0, phiL, rx0, 0, X, n * rx1, 0, 0.0, T1,
+         n * rx1, 0);
+    if (f.kind == 1)
+      mode_mix(s, T1, ry0, RL, n, rx1, f.Hd, RR, T2);
+    else
+      gemm(s, false, false, m * RR, rx1, RL * n, 1.0, Ap, RL * n, 0, T1, rx1,
+           (int64_t)RL * n * rx1, 0.0, T2, rx1, (int64_t)m * RR * rx1, ry0);
+  }
   gemm(s, true, false, ry1, RR * rx1, ry0 * m, 1.0, Y, ry1, 0, T2, RR * rx1, 0, 0.0, out,
        RR * rx1, 0);
 }
@@ -36,11 +48,23 @@ void iface_left(hipStream_t s, const double* phiL, const double* Y, int ry0, int
 // out[a, b, c] = sum Y[a, i, a2] A[b, i, j, b1] X[c, j, c2] PhiR[a2, b1, c2]
 void iface_right(hipStream_t s, const double* phiR, const double* Y, int ry0, int ry1,
                  const double* Ap, int RL, int m, int n, int RR, const double* X, int rx0,
-                 int rx1, double* out, double* T1, double* T2) {
+                 int rx1, double* out, double* T1, double* T2, const ModeForm& f = ModeForm{}) {
   gemm(s, false, false, ry0 * m, RR * rx1, ry1, 1.0, Y, ry1, 0, phiR, RR * rx1, 0, 0.0, T1,
        RR * rx1, 0);
-  gemm(s, true, false, RL * n, rx1, m * RR, 1.0, Ap, RL * n, 0, T1, rx1, (int64_t)m * RR * rx1,
-       0.0, T2, rx1, (int64_t)RL * n * rx1, ry0);
+  if (f.kind == 2) {
+    // T2[a][b, c2] = sum_{(i, b1)} Arp[(i, b1), b] T1[a][(i, b1), c2];
+    // out[(a, b), c] = sum_c2 T2[(a, b), c2] u[c, c2], u[c, c2] = sum_j w_j X[c, j, c2]
+    gemm(s, true, false, RL, rx1, m * RR, 1.0, f.Arp, RL, 0, T1, rx1, (int64_t)m * RR * rx1, 0.0,
+         T2, rx1, (int64_t)RL * rx1, ry0);
+    mode_contract(s, X, rx0, n, rx1, f.w, T1);
+    gemm(s, false, true, ry0 * RL, rx0, rx1, 1.0, T2, rx1, 0, T1, rx1, 0, 0.0, out, rx0, 0);
+    return;
+  }
+  if (f.kind == 1)
+    mode_mix_t(s, T1, ry0, n, RR, rx1, f.Hd, RL, T2);
+  else
+    gemm(s, true, false, RL * n, rx1, m * RR, 1.0, Ap, RL * n, 0, T1, rx1, (int64_t)m * RR * rx1,
+         0.0, T2, rx1, (int64_t)RL * n * rx1, ry0);
   gemm(s, false, true, ry0 * RL, rx0, n * rx1, 1.0, T2, n * rx1, 0, X, n * rx1, 0, 0.0, out,
        rx0, 0);
 }
@@ -70,6 +94,16 @@ void Solver::plan(Bump& b) {
     ApH[k] = b.d(H.size(k));
     ApA[k] = b.d(SF.size(k));
     ApI[k] = b.d(Id.size(k));
+  }
+  HdH.assign(dd, nullptr);
+  ArpSF.assign(dd, nullptr);
+  wSF.assign(dd, nullptr);
+  for (int k = 0; k < dd; ++k) {
+    if (Hdiag[k]) HdH[k] = b.d((int64_t)H.R[k] * n[k] * H.R[k + 1]);
+    if (sf_rank1[k]) {
+      ArpSF[k] = b.d((int64_t)n[k] * SF.R[k + 1] * SF.R[k]);
+      wSF[k] = b.d(n[k]);
+    }
   }
   // TT vectors
   auto carve_vec = [&](TTv& v, const std::vector<int>& cap) {
@@ -318,6 +352,77 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
               }
     Hdiag[k] = diag;
   }
+  // cores of S + F/k whose columns (in the mode) are multiples of one column:
+  // the angular integral sums every direction with the quadrature weights, so
+  // A[b, i, j, b'] = a[b, i, b'] w_j.  Core 0 is rebuilt each step as
+  // SF_0 + F_0 / k, so there both parts must share the weights.
+  sf_rank1.assign(d, 0);
+  sf_j0.assign(d, -1);
+  sf_w.assign(d, std::vector<double>());
+  auto col_form = [&](const std::vector<double>& a, int R0, int nn, int R1, int& j0,
+                      std::vector<double>& w) {
+    auto at = [&](int b, int i, int j, int c) {
+      return a[(((int64_t)b * nn + i) * nn + j) * R1 + c];
+    };
+    double amax = 0.0, best = -1.0;
+    for (double v : a) amax = std::max(amax, std::fabs(v));
+    if (amax == 0.0) return false;
+    for (int j = 0; j < nn; ++j) {
+      double t = 0.0;
+      for (int b = 0; b < R0; ++b)
+        for (int i = 0; i < nn; ++i)
+          for (int c = 0; c < R1; ++c) t += at(b, i, j, c) * at(b, i, j, c);
+      if (t > best) { best = t; j0 = j; }
+    }
+    w.assign(nn, 0.0);
+    for (int j = 0; j < nn; ++j) {
+      double t = 0.0;
+      for (int b = 0; b < R0; ++b)
+        for (int i = 0; i < nn; ++i)
+          for (int c = 0; c < R1; ++c) t += at(b, i, j, c) * at(b, i, j0, c);
+      w[j] = t / best;
+    }
+    const double cut = 1e-13 * amax;
+    for (int b = 0; b < R0; ++b)
+      for (int i = 0; i < nn; ++i)
+        for (int j = 0; j < nn; ++j)
+          for (int c = 0; c < R1; ++c)
+            if (std::fabs(at(b, i, j, c) - at(b, i, j0, c) * w[j]) > cut) return false;
+    return true;
+  };
+  for (int k = 0; k < d && rhs_mode == 0; ++k) {
+    if (n[k] <= 2) continue;
+    std::vector<double> a(SF.size(k));
+    TT_HIP(hipMemcpy(a.data(), SF.core(k), a.size() * sizeof(double), hipMemcpyDeviceToHost));
+    int j0 = -1;
+    std::vector<double> w;
+    bool ok = col_form(a, SF.R[k], n[k], SF.R[k + 1], j0, w);
+    if (ok && k == 0) {
+      // the F part with the same weights (and reference column)
+      std::vector<double> f(SF.size(0));
+      TT_HIP(hipMemcpy(f.data(), p->F_core0, f.size() * sizeof(double), hipMemcpyDeviceToHost));
+      int jf = -1;
+      std::vector<double> wf;
+      if (!col_form(f, SF.R[0], n[0], SF.R[1], jf, wf)) ok = false;
+      if (ok) {
+        double fmax = 0.0;
+        for (double v : f) fmax = std::max(fmax, std::fabs(v));
+        for (int b = 0; b < SF.R[0] && ok; ++b)
+          for (int i = 0; i < n[0] && ok; ++i)
+            for (int j = 0; j < n[0] && ok; ++j)
+              for (int c = 0; c < SF.R[1]; ++c) {
+                const double fij = f[(((int64_t)b * n[0] + i) * n[0] + j) * SF.R[1] + c];
+                const double fi0 = f[(((int64_t)b * n[0] + i) * n[0] + j0) * SF.R[1] + c];
+                if (std::fabs(fij - fi0 * w[j]) > 1e-13 * fmax) { ok = false; break; }
+              }
+      }
+    }
+    if (ok) {
+      sf_rank1[k] = 1;
+      sf_j0[k] = j0;
+      sf_w[k] = w;
+    }
+  }
   // dry run, allocate, carve
   Bump dry;
   plan(dry);
@@ -375,6 +480,24 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   // A(k) view: core 0 -> A0, others -> SF
   Ak = SF;
   Ak.off[0] = A0 - SF.data;
+  formH.assign(d, ModeForm{});
+  formSF.assign(d, ModeForm{});
+  formId.assign(d, ModeForm{});
+  for (int k = 0; k < d; ++k) {
+    if (Hdiag[k]) {
+      op_diag(s, H.core(k), H.R[k], n[k], H.R[k + 1], HdH[k]);
+      formH[k].kind = 1;
+      formH[k].Hd = HdH[k];
+    }
+    if (sf_rank1[k]) {
+      TT_HIP(hipMemcpy(wSF[k], sf_w[k].data(), n[k] * sizeof(double), hipMemcpyHostToDevice));
+      // core 0's row factor is taken from SF_0 + F_0 / k at every step
+      if (k > 0) rank1_rows(s, SF.core(k), SF.R[k], n[k], SF.R[k + 1], sf_j0[k], ArpSF[k]);
+      formSF[k].kind = 2;
+      formSF[k].Arp = ArpSF[k];
+      formSF[k].w = wSF[k];
+    }
+  }
 
   // vectors
   for (int k = 0; k < d; ++k) copy(s, cf_in.core(k), cF.core(k), cf_in.size(k));
@@ -411,12 +534,15 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
 }
 
 Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
-                         const std::vector<double*>& ApOp, StepStats& st) {
+                         const std::vector<double*>& ApOp, const std::vector<ModeForm>& fOp,
+                         StepStats& st) {
   const int rk = X.r[k], rk1 = X.r[k + 1], nk = n[k];
   const int vk = V.r[k], vk1 = V.r[k + 1];
   LocalOp xh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RXH[k + 1], rk1, rk1,
              (bool)Hdiag[k]};
   LocalOp xa{LXA[k], rk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RXA[k + 1], rk1, vk1};
+  xh.form = formH[k];
+  xa.form = fOp[k];
   const int64_t N = (int64_t)rk * nk * rk1;
   local_apply(s, xa, V.core(k), fvec, 1.0, 0.0, T1, T2);
   local_apply(s, xh, X.core(k), yvec, 1.0, 0.0, T1, T2);
@@ -483,6 +609,8 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   // enrichment: residual projected with X on the left and Z on the right
   LocalOp za{LXA[k], rk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RZA[k + 1], kz, vk1};
   LocalOp zh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RZH[k + 1], kz, rk1};
+  za.form = fOp[k];
+  zh.form = formH[k];
   local_apply(s, za, V.core(k), crz, 1.0, 0.0, T1, T2);
   local_apply(s, zh, yvec, crz, -1.0, 1.0, T1, T2);
   copy2d(s, crz, rows, kz, kz, U2 + rt, w);
@@ -499,19 +627,21 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
   const int zk = Z.r[k];
   LocalOp zza{LZA[k], zk, Rop[k], vk, ApOp[k], Aop.core(k), nk, nk, Rop[k + 1], RZA[k + 1], kz, vk1};
   LocalOp zzh{LZH[k], zk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RZH[k + 1], kz, rk1};
+  zza.form = fOp[k];
+  zzh.form = formH[k];
   local_apply(s, zza, V.core(k), zc, 1.0, 0.0, T1, T2);
   local_apply(s, zzh, yvec, zc, -1.0, 1.0, T1, T2);
   qr(s, zc, zk * nk, kz, kz, Z.core(k), kz, U2w, kz, tau);
   X.r[k + 1] = q;
   // left interfaces at bond k+1
   iface_left(s, LXH[k], X.core(k), rk, q, ApH[k], RH[k], nk, nk, RH[k + 1], X.core(k), rk, q,
-             LXH[k + 1], T1, T2);
+             LXH[k + 1], T1, T2, formH[k]);
   iface_left(s, LXA[k], X.core(k), rk, q, ApOp[k], Rop[k], nk, nk, Rop[k + 1], V.core(k), vk,
-             vk1, LXA[k + 1], T1, T2);
+             vk1, LXA[k + 1], T1, T2, fOp[k]);
   iface_left(s, LZH[k], Z.core(k), zk, kz, ApH[k], RH[k], nk, nk, RH[k + 1], X.core(k), rk, q,
-             LZH[k + 1], T1, T2);
+             LZH[k + 1], T1, T2, formH[k]);
   iface_left(s, LZA[k], Z.core(k), zk, kz, ApOp[k], Rop[k], nk, nk, Rop[k + 1], V.core(k), vk,
-             vk1, LZA[k + 1], T1, T2);
+             vk1, LZA[k + 1], T1, T2, fOp[k]);
 }
 
 double Solver::step_cost() const {
@@ -545,12 +675,14 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
   copy(s, F0, A0, SF.size(0));
   axpby_div(s, SF.size(0), 1.0, SF.core(0), 1.0, scal + KVAL, A0);
   permute_op(s, A0, SF.R[0], n[0], n[0], SF.R[1], ApA[0]);
+  if (formSF[0].kind == 2) rank1_rows(s, A0, SF.R[0], n[0], SF.R[1], sf_j0[0], ArpSF[0]);
   Bump w;
   w.base = rw;
   w.cap = rw_cap;
   const TTv* V = &psi;
   const TTm* Aop = &Ak;
   const std::vector<double*>* ApOp = &ApA;
+  const std::vector<ModeForm>* fOp = &formSF;
   if (rhs_mode == 1) {
     matvec(s, Ak, psi, B);
     w.used = 0;
@@ -558,6 +690,7 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
     V = &B;
     Aop = &Id;
     ApOp = &ApI;
+    fOp = &formId;
   }
   // warm start X = psi
   X.r = psi.r;
@@ -574,15 +707,15 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
     orth_right(s, Z, w);
     for (int k = d - 1; k >= 1; --k) {
       iface_right(s, RXH[k + 1], X.core(k), X.r[k], X.r[k + 1], ApH[k], RH[k], n[k], n[k],
-                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RXH[k], T1, T2);
+                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RXH[k], T1, T2, formH[k]);
       iface_right(s, RXA[k + 1], X.core(k), X.r[k], X.r[k + 1], (*ApOp)[k], Rop[k], n[k], n[k],
-                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RXA[k], T1, T2);
+                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RXA[k], T1, T2, (*fOp)[k]);
       iface_right(s, RZH[k + 1], Z.core(k), Z.r[k], Z.r[k + 1], ApH[k], RH[k], n[k], n[k],
-                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RZH[k], T1, T2);
+                  RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RZH[k], T1, T2, formH[k]);
       iface_right(s, RZA[k + 1], Z.core(k), Z.r[k], Z.r[k + 1], (*ApOp)[k], Rop[k], n[k], n[k],
-                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RZA[k], T1, T2);
+                  Rop[k + 1], V->core(k), V->r[k], V->r[k + 1], RZA[k], T1, T2, (*fOp)[k]);
     }
-    for (int k = 0; k < d; ++k) co_await sweep_core_co(s, k, *V, *Aop, *ApOp, st);
+    for (int k = 0; k < d; ++k) co_await sweep_core_co(s, k, *V, *Aop, *ApOp, *fOp, st);
     TT_HIP(hipMemcpyAsync(h_res, resarr, d * sizeof(double), hipMemcpyDeviceToHost, s));
     co_await Sync{&slot, s};
     max_res = 0.0;

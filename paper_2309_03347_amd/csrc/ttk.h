@@ -13,6 +13,18 @@ void local_matrix(hipStream_t s, const double* phiL, int ra, int RL, const doubl
 void scale_cols(hipStream_t s, double* X, int rows, int cols, int ld, const double* sv);
 // Hd[b][i][b'] = A[b, i, i, b']
 void op_diag(hipStream_t s, const double* A, int RL, int n, int RR, double* Hd);
+// Mode-diagonal core (A[b,i,j,b'] = delta_ij Hd[b,i,b']) in a contraction:
+//   out[a][i][b'][c] = sum_b Hd[b][i][b'] in[a][b][i][c]
+void mode_mix(hipStream_t s, const double* in, int ra, int RL, int n, int rc, const double* Hd,
+              int RR, double* out);
+//   out[a][b][i][c] = sum_b' Hd[b][i][b'] in[a][i][b'][c]
+void mode_mix_t(hipStream_t s, const double* in, int ra, int n, int RR, int rc, const double* Hd,
+                int RL, double* out);
+// u[a][c] = sum_j w[j] v[a][j][c]
+void mode_contract(hipStream_t s, const double* v, int ra, int n, int rc, const double* w,
+                   double* u);
+// Arp[(i*RR + b'), b] = A[b, i, j0, b'] (row factor of a core with proportional columns)
+void rank1_rows(hipStream_t s, const double* A, int RL, int n, int RR, int j0, double* Arp);
 // n block matrices M[i] ((ra rc) x (ra rc)) of a mode-diagonal local operator
 void local_matrix_diag(hipStream_t s, const double* phiL, int ra, int RL, const double* P, int n,
                        int rc, double* M);

@@ -77,6 +77,81 @@ __global__ void local_matrix_kernel(const double* __restrict__ phiL, int ra, int
   }
 }
 
+// Mode-diagonal core applied to a contracted operand (the middle stage of a
+// local product or interface update when A[b, i, j, b'] = delta_ij Hd[b, i, b']):
+//   out[a][i][b'][c] = sum_b Hd[b][i][b'] in[a][b][i][c]
+__global__ __launch_bounds__(256) void mode_mix_kernel(const double* __restrict__ in, int ra,
+                                                       int RL, int n, int rc,
+                                                       const double* __restrict__ Hd, int RR,
+                                                       double* __restrict__ out) {
+  const int64_t total = (int64_t)ra * n * RR * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % rc);
+    const int bp = (int)((e / rc) % RR);
+    const int i = (int)((e / ((int64_t)rc * RR)) % n);
+    const int a = (int)(e / ((int64_t)rc * RR * n));
+    const double* x = in + ((int64_t)a * RL * n + i) * rc + c;
+    const double* h = Hd + (int64_t)i * RR + bp;
+    double acc = 0.0;
+    for (int b = 0; b < RL; ++b) acc = fma(h[(int64_t)b * n * RR], x[(int64_t)b * n * rc], acc);
+    out[e] = acc;
+  }
+}
+
+// The transposed use (right interfaces):
+//   out[a][b][i][c] = sum_b' Hd[b][i][b'] in[a][i][b'][c]
+__global__ __launch_bounds__(256) void mode_mix_t_kernel(const double* __restrict__ in, int ra,
+                                                         int n, int RR, int rc,
+                                                         const double* __restrict__ Hd, int RL,
+                                                         double* __restrict__ out) {
+  const int64_t total = (int64_t)ra * RL * n * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % rc);
+    const int i = (int)((e / rc) % n);
+    const int b = (int)((e / ((int64_t)rc * n)) % RL);
+    const int a = (int)(e / ((int64_t)rc * n * RL));
+    const double* x = in + (((int64_t)a * n + i) * RR) * rc + c;
+    const double* h = Hd + ((int64_t)b * n + i) * RR;
+    double acc = 0.0;
+    for (int bp = 0; bp < RR; ++bp) acc = fma(h[bp], x[(int64_t)bp * rc], acc);
+    out[e] = acc;
+  }
+}
+
+// Weighted sum over the mode: u[a][c] = sum_j w[j] v[a][j][c]
+__global__ __launch_bounds__(256) void mode_contract_kernel(const double* __restrict__ v, int ra,
+                                                            int n, int rc,
+                                                            const double* __restrict__ w,
+                                                            double* __restrict__ u) {
+  const int64_t total = (int64_t)ra * rc;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % rc);
+    const int a = (int)(e / rc);
+    const double* x = v + (int64_t)a * n * rc + c;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc = fma(w[j], x[(int64_t)j * rc], acc);
+    u[e] = acc;
+  }
+}
+
+// Row factor of a core whose columns are multiples of one column j0
+// (A[b, i, j, b'] = a[b, i, b'] w_j with w_j0 = 1), as a GEMM operand:
+//   Arp[(i*RR + b'), b] = A[b, i, j0, b']
+__global__ void rank1_rows_kernel(const double* __restrict__ A, int RL, int n, int RR, int j0,
+                                  double* __restrict__ Arp) {
+  const int64_t total = (int64_t)n * RR * RL;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e % RL);
+    const int bp = (int)((e / RL) % RR);
+    const int i = (int)(e / ((int64_t)RL * RR));
+    Arp[e] = A[(((int64_t)b * n + i) * n + j0) * RR + bp];
+  }
+}
+
 // Diagonal of an operator core: Hd[b][i][b'] = A[b, i, i, b']
 __global__ void op_diag_kernel(const double* __restrict__ A, int RL, int n, int RR,
                                double* __restrict__ Hd) {
@@ -454,6 +529,41 @@ void local_matrix(hipStream_t s, const double* phiL, int ra, int RL, const doubl
   if (total <= 0) return;
   ++g_launches;
   local_matrix_kernel<<<grid_for(total, 256), 256, 0, s>>>(phiL, ra, RL, P, m, n, rc, M);
+  TT_HIP(hipGetLastError());
+}
+
+void mode_mix(hipStream_t s, const double* in, int ra, int RL, int n, int rc, const double* Hd,
+              int RR, double* out) {
+  const int64_t total = (int64_t)ra * n * RR * rc;
+  if (total <= 0) return;
+  ++g_launches;
+  mode_mix_kernel<<<grid_for(total, 256), 256, 0, s>>>(in, ra, RL, n, rc, Hd, RR, out);
+  TT_HIP(hipGetLastError());
+}
+
+void mode_mix_t(hipStream_t s, const double* in, int ra, int n, int RR, int rc, const double* Hd,
+                int RL, double* out) {
+  const int64_t total = (int64_t)ra * RL * n * rc;
+  if (total <= 0) return;
+  ++g_launches;
+  mode_mix_t_kernel<<<grid_for(total, 256), 256, 0, s>>>(in, ra, n, RR, rc, Hd, RL, out);
+  TT_HIP(hipGetLastError());
+}
+
+void mode_contract(hipStream_t s, const double* v, int ra, int n, int rc, const double* w,
+                   double* u) {
+  const int64_t total = (int64_t)ra * rc;
+  if (total <= 0) return;
+  ++g_launches;
+  mode_contract_kernel<<<grid_for(total, 256), 256, 0, s>>>(v, ra, n, rc, w, u);
+  TT_HIP(hipGetLastError());
+}
+
+void rank1_rows(hipStream_t s, const double* A, int RL, int n, int RR, int j0, double* Arp) {
+  const int64_t total = (int64_t)n * RR * RL;
+  if (total <= 0) return;
+  ++g_launches;
+  rank1_rows_kernel<<<grid_for(total, 256), 256, 0, s>>>(A, RL, n, RR, j0, Arp);
   TT_HIP(hipGetLastError());
 }
 

@@ -104,3 +104,29 @@ def test_power_steps_32cube_four_groups_error_at_rank_caps(cuda):
         worst[cap] = max(errs)
         s.close()
     assert worst[64] < worst[32]
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.inner_box(l=2, G=2, N=8, seed=23, rmax=256, tol=1e-10),   # angle = core 1
+    lambda: W.homogeneous(l=3, N=8, seed=24, rmax=256, tol=1e-10),       # angle = core 0
+], ids=["G2_S8_angle_core1", "G1_S8_angle_core0"])
+def test_power_steps_match_oracle_s8(cuda, maker):
+    # 80 directions: the angle core's contractions use its structure (H
+    # diagonal in the direction, S and F summing directions with the weights;
+    # with one group the angle core is core 0, whose S + F/k factor changes
+    # with k at every step)
+    from paper_2309_03347_amd.solver import KeffSolver
+    wl = maker()
+    s = KeffSolver(wl, kick=8, max_sweeps=60)
+    prob = sweep.Problem.from_workload(wl)
+    psi = OT.full_vec(s.native.psi().cores())
+    k = 1.0
+    for step in range(3):
+        print(f"{wl.name} step {step}", flush=True)
+        rec = s.step()
+        ref, kref = prob.power_step(psi, k)
+        got = OT.full_vec(s.psi_cores())
+        assert abs(rec.k - kref) <= 1e-8 * abs(kref), (step, rec.k, kref)
+        assert np.linalg.norm(_unit(got) - _unit(ref)) <= 1e-6, step
+        psi, k = got, rec.k
+    s.close()
