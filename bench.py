@@ -1,8 +1,12 @@
 """Benchmark: TT/QTT power-iteration steps per second on one MI355X.
 
-Workload (default): 32^3 nodes, 4 energy groups, S4 level-symmetric
-(24 directions), vacuum boundaries, two-region material with a seeded
-random inner box, TT rank cap 32, truncation tolerance 1e-8, FP64.
+Workload (default): 128^3 nodes, 8 energy groups, S8 level-symmetric
+(80 directions), vacuum boundaries, 4 x 4 x 4 checkerboard of four seeded
+materials, TT rank cap 64, truncation tolerance 1e-8, FP64, with the mixed
+run of the same input next to it.  The largest configuration (1024^3 nodes,
+16 groups, S16, eight materials with upscatter, rank cap 96) is measured in
+the same line with a few steps (`largest_config`): one of its steps takes
+tens of seconds, too long for the K-step contract of the headline.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
 
@@ -52,6 +56,13 @@ def _measured_traffic(kernel, workload):
 
 WORKLOADS = {
     # name: (builder, description)
+    "checkerboard_n1024_G16_S16": (lambda W: W.config(4),
+                                   "1024^3 nodes, 16 groups, S16 (288 dirs), 2x2x2 blocks of 8 "
+                                   "materials, upscatter in the lowest 4 groups, rank cap 96, "
+                                   "tol 1e-7"),
+    "checkerboard_n128_G8_S8": (lambda W: W.config(2),
+                                "128^3 nodes, 8 groups, S8 (80 dirs), 4x4x4 checkerboard of 4 "
+                                "materials, rank cap 64, tol 1e-8"),
     "inner_box_n32_G4_S4": (lambda W: W.config(1),
                             "32^3 nodes, 4 groups, S4 (24 dirs), two-region, rank cap 32, tol 1e-8"),
     "homogeneous_n8_S2": (lambda W: W.config(0),
@@ -66,7 +77,7 @@ def _parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--workload", default="inner_box_n32_G4_S4", choices=sorted(WORKLOADS))
+    p.add_argument("--workload", default="checkerboard_n128_G8_S8", choices=sorted(WORKLOADS))
     p.add_argument("--rmax", type=int, default=0, help="override the rank cap (0: workload's)")
     p.add_argument("--rhs-mode", type=int, default=0, help="0 projected, 1 explicit")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -78,29 +89,73 @@ def _parse():
     p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision comparison run")
-    p.add_argument("--ttk-steps", type=int, default=60,
+    p.add_argument("--ttk-steps", type=int, default=20,
                    help="step limit of the time-to-k run (0 skips it)")
+    p.add_argument("--probe-steps", type=int, default=5,
+                   help="steps of the kernel-probe pass (at most --steps)")
+    p.add_argument("--largest-steps", type=int, default=2,
+                   help="timed steps of the largest configuration (0 skips it)")
+    p.add_argument("--largest-warmup", type=int, default=1)
     return p.parse_args()
 
 
-def _cpu_baseline(wl, seconds: float):
-    """The checker's exact power iteration, timed for about `seconds`."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of the checker's runtime (libgomp)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def _cpu_baseline(wl, seconds: float, host_budget_gb: float = 120.0):
+    """The checker's exact power iteration on the host, timed for about
+    `seconds` (at least one step), all host threads and one thread."""
     import numpy as np
     from oracle import sweep
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n_unknowns = wl.G * wl.L * wl.n ** 3
+    base = dict(unit="steps/s", cores=threads, kind="oracle", cpu_model=_cpu_model())
+    # the dense iteration holds about four flux-sized arrays
+    need_gb = 4 * 8 * n_unknowns / 1e9
+    if need_gb > host_budget_gb:
+        return dict(base, value=None, single_thread=None,
+                    sample=f"not runnable: one dense flux vector of this workload "
+                           f"({n_unknowns:.3g} unknowns) is {8 * n_unknowns / 1e12:.1f} TB")
     prob = sweep.Problem.from_workload(wl)
     psi = sweep.dense_psi0(wl)
-    k = 1.0
-    nxt, k = prob.power_step(psi, k)           # warm (page-in, thread pool)
-    psi = nxt / np.linalg.norm(nxt)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        nxt, k = prob.power_step(psi, k)
-        psi = nxt / np.linalg.norm(nxt)
-        steps += 1
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
+
+    def run(limit):
+        nonlocal psi
+        k = 1.0
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            nxt, k = prob.power_step(psi, k)
+            psi = nxt / np.linalg.norm(nxt)
+            steps += 1
+            dt = time.perf_counter() - t0
+            if dt >= limit:
+                return steps, dt
+
+    steps, dt = run(seconds)
+    single = None
+    if dt / steps < 1.0 and _omp_threads(1):
+        s1, d1 = run(seconds / 2)
+        _omp_threads(threads)
+        single = dict(value=s1 / d1, sample=f"{s1} steps in {d1:.1f} s on one thread")
+    return dict(base, value=steps / dt, single_thread=single,
                 sample=f"{steps} exact sweep power steps of the same workload "
                        f"({prob.n_unknowns} unknowns) in {dt:.1f} s")
 
@@ -216,6 +271,42 @@ def _bench_batch(args):
     print("solvers closed", file=sys.stderr, flush=True)
 
 
+def _largest(args):
+    """A few FP64 steps of the 1024^3, 16-group, S16 configuration."""
+    import torch
+    from paper_2309_03347_amd import workload as W
+    from paper_2309_03347_amd.solver import KeffSolver
+    name = "checkerboard_n1024_G16_S16"
+    builder, desc = WORKLOADS[name]
+    wl = builder(W)
+    t0 = time.perf_counter()
+    s = KeffSolver(wl)
+    setup = time.perf_counter() - t0
+    print(f"{name}: setup {setup:.1f} s", file=sys.stderr, flush=True)
+    for i in range(args.largest_warmup):
+        rec = s.step()
+        print(f"{name}: warmup step {i} {rec.seconds:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.largest_steps):
+        rec = s.step()
+        print(f"{name}: timed step {i} {rec.seconds:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h = s.history
+    out = dict(workload=name, description=desc, value=args.largest_steps / dt, unit="steps/s",
+               steps=args.largest_steps, warmup=args.largest_warmup,
+               ms_per_step=1e3 * dt / args.largest_steps, dtype="f64",
+               unknowns=float(wl.G * wl.L * wl.n ** 3), rank_cap=wl.rmax, tol=wl.tol,
+               setup_seconds=setup, k=h[-1].k, dk_last=h[-1].dk,
+               max_rank=int(max(s.native.ranks())), sweeps=[r.sweeps for r in h],
+               local_iters=[r.local_iters for r in h],
+               cpu_baseline=_cpu_baseline(wl, args.cpu_seconds) if not args.no_cpu_baseline
+               else None)
+    s.close()
+    return out
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -248,7 +339,7 @@ def main():
     probe = None
     if not args.no_probe:
         s.native.set_probe(True)
-        for _ in range(args.steps):
+        for _ in range(max(1, min(args.steps, args.probe_steps))):
             s.step()
         torch.cuda.synchronize()
         probe = s.native.probe_stats()
@@ -310,6 +401,10 @@ def main():
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(wl, args.cpu_seconds)
 
+    largest = None
+    if args.largest_steps > 0 and args.workload != "checkerboard_n1024_G16_S16":
+        largest = _largest(args)
+
     out = {
         "metric": "power-iteration steps/sec & time-to-k at 1e-5, mixed vs FP64; TT GFLOP/s % peak",
         "value": value,
@@ -325,7 +420,8 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": args.workload, "description": desc, "rank_cap": rmax,
                    "tol": wl.tol, "rhs_mode": "projected" if args.rhs_mode == 0 else "explicit",
-                   "unknowns": int(wl.G * wl.L * wl.n ** 3)},
+                   "unknowns": int(wl.G * wl.L * wl.n ** 3),
+                   "quadrature": "level-symmetric points, LQn weights"},
         "k": hist[-1].k,
         "dk_last": hist[-1].dk,
         "max_rank": int(max(s.native.ranks())),
@@ -335,6 +431,7 @@ def main():
         "time_to_k": ttk,
         "time_to_k_small": ttk_small,
         "mixed": mixed,
+        "largest_config": largest,
     }
     if probe is not None:
         out["kernel_probe"] = {k: dict(launches=v["launches"], ms=round(v["total_ms"], 3))

@@ -163,8 +163,13 @@ typedef struct {
   int32_t max_iter;     /* total GMRES iterations */
   int32_t restart;      /* Krylov dimension per cycle */
   int32_t direct_max;   /* auto: LU up to this many unknowns */
-  int32_t precision;    /* GMRES (method 2): 0 FP64; 1 mixed - FP32 Arnoldi cycles as
-                           iterative refinement of the FP64 residual, converged in FP64 */
+  int32_t precision;    /* GMRES: 0 FP64; 1 mixed - the persistent kernel runs FP32
+                           Arnoldi cycles as iterative refinement of the FP64 residual;
+                           2 as 1, and GMRES outside the persistent kernel (method 4, or
+                           method 2 for systems it cannot hold) runs its operator products
+                           on the BF16 matrix cores with FP32 accumulation inside each
+                           restart cycle (a cycle ends at a 1e-2 reduction), with the FP64
+                           residual at every restart; all converge in FP64 to tol */
 } tt_solve_opts;
 
 typedef struct {
@@ -174,6 +179,21 @@ typedef struct {
 } tt_solve_info;
 
 size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts);
+
+/*
+ * tt_local_apply - the local operator of tt_local_solve applied to a vector,
+ *     y = sum_{b,b'} PhiL[:, b, :] (x) A_k[b, :, :, b'] (x) PhiR[:, b', :]  x
+ * (the matrix-vector product inside the local Krylov solve, Section 3.3), as
+ * three contractions: PhiL with x, the core, PhiR.  sys->f is not used.
+ * precision 0: FP64; 2: the contractions on the BF16 matrix cores (operands
+ * rounded to BF16, FP32 accumulation, FP64 result).  x [ra][n][rc] and y
+ * [ra][m][rc] are device arrays; y is overwritten.  `ws` at least
+ * tt_local_apply_workspace(sys) bytes.  Synchronizes `stream`.
+ */
+size_t tt_local_apply_workspace(const tt_local* sys);
+tt_status tt_local_apply(const tt_local* sys, const double* x, double* y, int32_t precision,
+                         void* ws, size_t ws_bytes, tt_stream stream);
+
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,
                          tt_solve_info* info, void* ws, size_t ws_bytes, tt_stream stream);
 
@@ -248,14 +268,18 @@ typedef struct {
   int32_t gmres_restart;
   int32_t gmres_max_iter;
   int32_t direct_max;    /* local systems up to this size use dense LU */
-  int32_t precision;     /* local GMRES: 0 FP64, 1 mixed (FP32 Arnoldi, FP64 refinement);
-                            everything else in the step stays FP64 */
+  int32_t precision;     /* local GMRES: 0 FP64, 1 mixed (FP32 Arnoldi, FP64 refinement),
+                            2 mixed with BF16 matrix-core products in the multi-launch GMRES
+                            (as tt_solve_opts.precision); everything else in the step
+                            (interfaces, QR, SVD, k) stays FP64 */
   /* Sweeping while the rank cap binds (the truncation error then exceeds
      tol, so the sweeps stop at stagnation instead of at tol): */
   int32_t min_sweeps;    /* sweeps before the stagnation test may stop (0: 2) */
   double cap_eta;        /* local solves reduce their residual by this factor (0: 1e-2) */
   double stall;          /* stop when the largest local residual falls by less than this
                             factor over a sweep (0: 0.5) */
+  int32_t krylov_path;   /* local GMRES: 0 the persistent kernel where it fits, 1 always
+                            the multi-launch form (one launch per stage of each step) */
 } tt_solver_opts;
 
 typedef struct {

@@ -97,8 +97,9 @@ LocalSolveOpts solve_opts_from(const tt_solve_opts* o) {
     so.max_iter = o->max_iter > 0 ? o->max_iter : 1000;
     so.restart = o->restart > 0 ? o->restart : 80;
     so.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
-    TT_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 or 1");
-    so.mixed = o->precision == 1;
+    TT_REQUIRE(o->precision >= 0 && o->precision <= 2, "precision must be 0, 1 or 2");
+    so.mixed = o->precision >= 1;
+    so.lowp = o->precision == 2;
   }
   return so;
 }
@@ -269,6 +270,43 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts) 
   LocalSolveOpts so = solve_opts_from(opts);
   const size_t ap = (size_t)sys->RL * sys->m * sys->n * sys->RR;
   return (local_solve_ws_doubles(op, so) + ap + 64) * sizeof(double) + 8192;
+}
+
+size_t tt_local_apply_workspace(const tt_local* sys) {
+  if (!sys) return 0;
+  const size_t ap = (size_t)sys->RL * sys->m * sys->n * sys->RR;
+  const size_t t1 = (size_t)sys->ra * sys->RL * sys->n * sys->rc;
+  const size_t t2 = (size_t)sys->ra * sys->m * sys->RR * sys->rc;
+  return (ap + t1 + t2 + 3 * 64) * sizeof(double) + 1024;
+}
+
+tt_status tt_local_apply(const tt_local* sys, const double* x, double* y, int32_t precision,
+                         void* ws, size_t ws_bytes, tt_stream stream) {
+  return guard([&] {
+    TT_REQUIRE(sys && x && y && ws, "NULL system, x, y or workspace");
+    TT_REQUIRE(sys->phiL && sys->A && sys->phiR, "NULL field in system");
+    TT_REQUIRE(sys->ra >= 1 && sys->RL >= 1 && sys->m >= 1 && sys->n >= 1 && sys->RR >= 1 &&
+                   sys->rc >= 1,
+               "dimensions must be >= 1");
+    TT_REQUIRE(precision == 0 || precision == 2, "precision must be 0 (FP64) or 2 (BF16)");
+    if (ws_bytes < tt_local_apply_workspace(sys))
+      throw CapacityError{"workspace smaller than tt_local_apply_workspace"};
+    hipStream_t s = (hipStream_t)stream;
+    Bump w;
+    w.base = (char*)ws;
+    w.cap = ws_bytes;
+    double* Ap = w.d((size_t)sys->RL * sys->m * sys->n * sys->RR);
+    double* T1 = w.d((size_t)sys->ra * sys->RL * sys->n * sys->rc);
+    double* T2 = w.d((size_t)sys->ra * sys->m * sys->RR * sys->rc);
+    permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
+    LocalOp op = local_op_from(sys);
+    op.Ap = Ap;
+    if (precision == 2)
+      local_apply_lp(s, op, x, y, 1.0, 0.0, T1, T2);
+    else
+      local_apply(s, op, x, y, 1.0, 0.0, T1, T2);
+    TT_HIP(hipStreamSynchronize(s));
+  });
 }
 
 tt_status tt_local_solve(const tt_local* sys, double* x, const tt_solve_opts* opts,

@@ -179,6 +179,14 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, co
   }
 }
 
+void splitk_reduce(hipStream_t s, const double* P, int nsplit, int batch, int M, int N,
+                   double alpha, double beta, double* C, int ldc, int64_t sC) {
+  ++g_launches;
+  splitk_reduce_kernel<<<grid_for((int64_t)M * N * batch, 256), 256, 0, s>>>(
+      P, nsplit, batch, M, N, alpha, beta, C, ldc, sC);
+  TT_HIP(hipGetLastError());
+}
+
 void transpose(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst,
                int ldd) {
   if (rows <= 0 || cols <= 0) return;

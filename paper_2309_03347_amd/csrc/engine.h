@@ -103,6 +103,9 @@ struct LocalOp {
 };
 void local_apply(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
                  double beta, double* T1, double* T2);
+// The same product with its GEMMs on the BF16 matrix cores (FP32 accumulation).
+void local_apply_lp(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
+                    double beta, double* T1, double* T2);
 
 struct LocalSolveOpts {
   int method = 0;          // 0 auto, 1 dense LU, 2 GMRES (persistent), 3 block LU, 4 GMRES (per-stage launches)
@@ -114,6 +117,10 @@ struct LocalSolveOpts {
   int block_max = 1024;    // auto: mode-diagonal cores solved as n blocks up to this size
   bool mixed = false;      // persistent GMRES: FP32 Arnoldi, FP64 residual refinement
   double inner_tol = 1e-5; // mixed: an FP32 cycle ends once its residual fell by this factor
+  bool persistent = true;  // GMRES may use the persistent kernel (false: multi-launch only)
+  bool lowp = false;       // multi-launch GMRES: operator products on the BF16 matrix cores
+                           // inside each restart cycle, FP64 residual at every restart
+  double inner_tol_lp = 1e-2;  // lowp: a cycle ends once its residual fell by this factor
 };
 struct LocalSolveResult {
   int iterations = 0;

@@ -272,34 +272,49 @@ void orth_right(hipStream_t s, TTv& x, Bump& ws) {
 // ---------------------------------------------------------------------------
 // Local operator and local solve
 // ---------------------------------------------------------------------------
-void local_apply(hipStream_t s, const LocalOp& o, const double* v, double* y, double alpha,
-                 double beta, double* T1, double* T2) {
+namespace {
+typedef void (*GemmFn)(hipStream_t, bool, bool, int, int, int, double, const double*, int,
+                       int64_t, const double*, int, int64_t, double, double*, int, int64_t, int);
+
+void local_apply_with(GemmFn mm, hipStream_t s, const LocalOp& o, const double* v, double* y,
+                      double alpha, double beta, double* T1, double* T2) {
   if (o.form.kind == 2) {
     // proportional columns: the mode of v is summed with w first
     // u[b2, d'] = sum_j w_j v[b2, j, d'] (held in T2 until T2 is rewritten)
     mode_contract(s, v, o.rb, o.n, o.rd, o.form.w, T2);
     // T1[(a, b), d'] = sum_{b2} PhiL[(a, b), b2] u[b2, d']
-    gemm(s, false, false, o.ra * o.RL, o.rd, o.rb, 1.0, o.phiL, o.rb, 0, T2, o.rd, 0, 0.0, T1,
-         o.rd, 0);
+    mm(s, false, false, o.ra * o.RL, o.rd, o.rb, 1.0, o.phiL, o.rb, 0, T2, o.rd, 0, 0.0, T1,
+         o.rd, 0, 1);
     // T2[a][(i, b'), d'] = sum_b Arp[(i, b'), b] T1[a][b, d']
-    gemm(s, false, false, o.m * o.RR, o.rd, o.RL, 1.0, o.form.Arp, o.RL, 0, T1, o.rd,
+    mm(s, false, false, o.m * o.RR, o.rd, o.RL, 1.0, o.form.Arp, o.RL, 0, T1, o.rd,
          (int64_t)o.RL * o.rd, 0.0, T2, o.rd, (int64_t)o.m * o.RR * o.rd, o.ra);
   } else {
     // T1[(a, b), (j, d')] = sum_{b2} PhiL[(a, b), b2] v[b2, (j, d')]
-    gemm(s, false, false, o.ra * o.RL, o.n * o.rd, o.rb, 1.0, o.phiL, o.rb, 0, v, o.n * o.rd, 0,
-         0.0, T1, o.n * o.rd, 0);
+    mm(s, false, false, o.ra * o.RL, o.n * o.rd, o.rb, 1.0, o.phiL, o.rb, 0, v, o.n * o.rd, 0,
+         0.0, T1, o.n * o.rd, 0, 1);
     if (o.form.kind == 1) {
       // diagonal in the mode: T2[a][i][b'][d'] = sum_b Hd[b, i, b'] T1[a][b][i][d']
       mode_mix(s, T1, o.ra, o.RL, o.n, o.rd, o.form.Hd, o.RR, T2);
     } else {
       // T2[a][(i, b'), d'] = sum_{(b, j)} Ap[(i, b'), (b, j)] T1[a][(b, j), d']
-      gemm(s, false, false, o.m * o.RR, o.rd, o.RL * o.n, 1.0, o.Ap, o.RL * o.n, 0, T1, o.rd,
+      mm(s, false, false, o.m * o.RR, o.rd, o.RL * o.n, 1.0, o.Ap, o.RL * o.n, 0, T1, o.rd,
            (int64_t)o.RL * o.n * o.rd, 0.0, T2, o.rd, (int64_t)o.m * o.RR * o.rd, o.ra);
     }
   }
   // y[(a, i), c] = sum_{(b', d')} T2[(a, i), (b', d')] PhiR[c, (b', d')]
-  gemm(s, false, true, o.ra * o.m, o.rc, o.RR * o.rd, alpha, T2, o.RR * o.rd, 0, o.phiR,
-       o.RR * o.rd, 0, beta, y, o.rc, 0);
+  mm(s, false, true, o.ra * o.m, o.rc, o.RR * o.rd, alpha, T2, o.RR * o.rd, 0, o.phiR,
+       o.RR * o.rd, 0, beta, y, o.rc, 0, 1);
+}
+}  // namespace
+
+void local_apply(hipStream_t s, const LocalOp& o, const double* v, double* y, double alpha,
+                 double beta, double* T1, double* T2) {
+  local_apply_with(gemm, s, o, v, y, alpha, beta, T1, T2);
+}
+
+void local_apply_lp(hipStream_t s, const LocalOp& o, const double* v, double* y, double alpha,
+                    double beta, double* T1, double* T2) {
+  local_apply_with(gemm_bf16, s, o, v, y, alpha, beta, T1, T2);
 }
 
 static int pick_method(const LocalOp& op, const LocalSolveOpts& o) {
@@ -398,7 +413,7 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     local_matrix(s, op.phiL, op.ra, op.RL, P, op.m, op.n, op.rc, M);
     copy(s, f, x, N);
     lu_solve(s, M, (int)N, (int)N, x);
-  } else if (method == 2 && krylov_enabled() &&
+  } else if (method == 2 && krylov_enabled() && o.persistent &&
              krylov_fits(KrylovShape{op.ra, op.RL, op.n, op.RR, op.rc},
                          std::max(2, std::min(o.restart, 88)))) {
     res.method = 2;
@@ -457,29 +472,39 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
         conv = host[0] <= target;
         break;
       }
+      // With lowp each restart cycle is one step of iterative refinement: the
+      // cycle's products run on the BF16 matrix cores and it ends once its own
+      // residual estimate fell by inner_tol_lp; the FP64 residual of the next
+      // restart decides convergence.
+      const double cycle_tgt = o.lowp ? std::max(target, o.inner_tol_lp * host[0]) : target;
+      bool cycle_done = false;
       // Arnoldi steps; the residual estimates are read back every kCheck
       // steps and the solution uses the first step that met the target.
       constexpr int kCheck = 4;
       int j = 0;
-      while (j < m && total < o.max_iter && !conv) {
+      while (j < m && total < o.max_iter && !cycle_done) {
         const int j0 = j;
         for (int q = 0; q < kCheck && j < m && total < o.max_iter; ++q, ++j, ++total) {
-          local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
+          if (o.lowp)
+            local_apply_lp(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
+          else
+            local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
           arnoldi_mwg(s, V, N, j, Hc, m + 1, cs, sn, g, resv, awork);
         }
         double est[kCheck];
         TT_HIP(hipMemcpyAsync(est, resv + j0, (j - j0) * sizeof(double), hipMemcpyDeviceToHost, s));
         TT_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < j - j0; ++q)
-          if (est[q] <= target) {
+          if (est[q] <= cycle_tgt) {
             total -= (j - j0) - (q + 1);
             j = j0 + q + 1;
-            conv = true;
+            cycle_done = true;
             break;
           }
       }
+      if (cycle_done && !o.lowp) conv = true;
       gmres_update(s, V, N, j, Hc, m + 1, g, x);
-      if (conv || total >= o.max_iter) break;
+      if (conv || (total >= o.max_iter && !o.lowp)) break;
     }
     res.iterations = total;
     res.converged = conv;

@@ -18,6 +18,16 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, co
           int lda, int64_t sA, const double* B, int ldb, int64_t sB, double beta, double* C,
           int ldc, int64_t sC, int batch = 1);
 
+// The same product on the BF16 matrix cores: operands rounded to BF16 as they
+// are staged, FP32 accumulation, FP64 result (lowp.hip).
+void gemm_bf16(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+               const double* A, int lda, int64_t sA, const double* B, int ldb, int64_t sB,
+               double beta, double* C, int ldc, int64_t sC, int batch = 1);
+// C[b][m][n] = alpha * sum_s P[s][b][m][n] + beta * C[b][m][n], s in order (split-K partials
+// of nsplit x batch dense M x N blocks).
+void splitk_reduce(hipStream_t s, const double* P, int nsplit, int batch, int M, int N,
+                   double alpha, double beta, double* C, int ldc, int64_t sC);
+
 // dst[j][i] = src[i][j] for an rows x cols source (row-major, leading dims given).
 void transpose(hipStream_t s, const double* src, int rows, int cols, int lds, double* dst,
                int ldd);

@@ -14,7 +14,7 @@ struct KrylovShape {
 
 // Largest grid of the persistent kernel (workgroups of 256 threads); each
 // workgroup owns ceil(r0 / grid) left-rank slices.  TTNT_KRYLOV_GRID overrides.
-constexpr int kKrylovMaxGrid = 64;
+constexpr int kKrylovMaxGrid = 256;
 
 // Grid cap in use (kKrylovMaxGrid unless overridden).
 int krylov_grid();

@@ -7,7 +7,7 @@ namespace ttnt {
 
 // Kernel classes timed by the probe.
 enum ProbeClass { kProbeGemmNN = 0, kProbeGemmTN, kProbeGemmNT, kProbeGemmTT, kProbeArnoldi,
-                  kProbeMatvec, kProbeKrylov, kProbeClasses };
+                  kProbeMatvec, kProbeKrylov, kProbeGemmBf16, kProbeClasses };
 
 struct Probe {
   bool active = false;

@@ -292,14 +292,17 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   lso.restart = o->gmres_restart > 0 ? o->gmres_restart : 80;
   lso.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
   lso.eta = 0.0;
-  TT_REQUIRE(o->precision == 0 || o->precision == 1, "precision must be 0 or 1");
+  TT_REQUIRE(o->precision >= 0 && o->precision <= 2, "precision must be 0, 1 or 2");
   TT_REQUIRE(o->min_sweeps >= 0 && o->cap_eta >= 0.0 && o->cap_eta < 1.0 && o->stall >= 0.0 &&
                  o->stall <= 1.0,
              "bad sweep-stopping options");
   if (o->min_sweeps > 0) min_sweeps = o->min_sweeps;
   if (o->cap_eta > 0.0) cap_eta = o->cap_eta;
   if (o->stall > 0.0) stall = o->stall;
-  lso.mixed = o->precision == 1;
+  lso.mixed = o->precision >= 1;
+  lso.lowp = o->precision == 2;
+  TT_REQUIRE(o->krylov_path == 0 || o->krylov_path == 1, "krylov_path must be 0 or 1");
+  lso.persistent = o->krylov_path == 0;
   // identity operator (explicit mode right-hand side)
   Id.d = d;
   Id.m = n;

@@ -25,7 +25,8 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_create", "tt_power_step", "tt_solver_get_psi", "tt_solver_ranks",
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
-            "ttnt_set_grid_wait_limit", "tt_orth_right"]
+            "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
+            "tt_local_apply"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -82,7 +83,7 @@ class TTSolverOpts(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int32), ("gmres_max_iter", ctypes.c_int32),
                 ("direct_max", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("min_sweeps", ctypes.c_int32), ("cap_eta", ctypes.c_double),
-                ("stall", ctypes.c_double)]
+                ("stall", ctypes.c_double), ("krylov_path", ctypes.c_int32)]
 
 
 class TTProbeStats(ctypes.Structure):
@@ -92,7 +93,7 @@ class TTProbeStats(ctypes.Structure):
 
 
 PROBE_CLASSES = {0: "gemm_nn", 1: "gemm_tn", 2: "gemm_nt", 3: "gemm_tt", 4: "arnoldi",
-                 5: "core_matvec", 6: "krylov"}
+                 5: "core_matvec", 6: "krylov", 7: "gemm_bf16"}
 
 
 class TTStepInfo(ctypes.Structure):
@@ -135,6 +136,10 @@ def lib():
                                              ctypes.POINTER(TTSolveInfo), v]
         L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
         L.tt_orth_right.argtypes = [ctypes.POINTER(TTVec), v, ctypes.c_size_t, v]
+        L.tt_local_apply_workspace.argtypes = [ctypes.POINTER(TTLocal)]
+        L.tt_local_apply_workspace.restype = ctypes.c_size_t
+        L.tt_local_apply.argtypes = [ctypes.POINTER(TTLocal), v, v, ctypes.c_int32, v,
+                                     ctypes.c_size_t, v]
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
@@ -151,7 +156,7 @@ def lib():
         for name in EXPORTED:
             if name not in ("ttnt_version", "tt_last_error", "tt_round_workspace",
                             "tt_dot_workspace", "tt_local_solve_workspace",
-                            "tt_solver_launches"):
+                            "tt_solver_launches", "tt_local_apply_workspace"):
                 getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -320,6 +325,25 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
                    converged=st == TT_OK)
 
 
+def tt_local_apply(phiL, A, phiR, x, precision: int = 0):
+    """y = (PhiL (x) A (x) PhiR) x; tensors are float64 CUDA tensors.  precision 2: BF16."""
+    torch = _torch()
+    ra, RL, _ = phiL.shape
+    RL2, m, n, RR = A.shape
+    rc = phiR.shape[0]
+    tensors = [t.contiguous() for t in (phiL, A, phiR)]
+    xc = x.contiguous()
+    y = torch.empty((ra, m, rc), dtype=torch.float64, device=x.device)
+    sysd = TTLocal(ra, RL, m, n, RR, rc, *[ctypes.c_void_p(t.data_ptr()) for t in tensors],
+                   ctypes.c_void_p(0))
+    ws = _workspace(lib().tt_local_apply_workspace(ctypes.byref(sysd)))
+    _check(lib().tt_local_apply(ctypes.byref(sysd), ctypes.c_void_p(xc.data_ptr()),
+                                ctypes.c_void_p(y.data_ptr()), int(precision),
+                                ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel() * 8),
+                                _stream()))
+    return y
+
+
 def tt_local_solve_noalloc(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
                            max_iter: int = 1000, restart: int = 80, direct_max: int = 256,
                            precision: int = 0):
@@ -377,14 +401,14 @@ class Solver:
                  max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  local_tol: float = 0.0, gmres_restart: int = 80, gmres_max_iter: int = 2000,
                  direct_max: int = 256, precision: int = 0, min_sweeps: int = 0,
-                 cap_eta: float = 0.0, stall: float = 0.0):
+                 cap_eta: float = 0.0, stall: float = 0.0, krylov_path: int = 0):
         self._hold = (H, SF, F_core0, cF, psi0)
         prob = TTProblem(H.desc(), SF.desc(), ctypes.c_void_p(F_core0.data_ptr()), cF.desc(),
                          psi0.desc(), float(k0))
         opts = TTSolverOpts(float(tol), int(rmax), int(kick), int(max_sweeps), int(rhs_mode),
                             int(rhs_rmax), float(local_tol), int(gmres_restart),
                             int(gmres_max_iter), int(direct_max), int(precision),
-                            int(min_sweeps), float(cap_eta), float(stall))
+                            int(min_sweeps), float(cap_eta), float(stall), int(krylov_path))
         h = ctypes.c_void_p()
         _check(lib().tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)))
         self.h = h

@@ -1,8 +1,9 @@
-"""k-eigenvalue power iteration on the device (host driver).
+"""k- and alpha-eigenvalue iterations on the device (host drivers).
 
 ``KeffSolver`` assembles the operators once (host setup, ``operators``),
 uploads them, and advances eq. TT_k_eff_fixed_points one step per
-``tt_power_step`` call of libttnt.so.
+``tt_power_step`` call of libttnt.so.  ``AlphaSolver`` runs the outer
+alpha iteration of eq. alpha_eig_fixed_points around converged k solves.
 """
 from __future__ import annotations
 
@@ -66,7 +67,8 @@ class KeffSolver:
     def __init__(self, wl, rmax: Optional[int] = None, tol: Optional[float] = None,
                  kick: int = 4, max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  direct_max: int = 256, gmres_restart: int = 80, ops=None, precision: int = 0,
-                 min_sweeps: int = 0, cap_eta: float = 0.0, stall: float = 0.0):
+                 min_sweeps: int = 0, cap_eta: float = 0.0, stall: float = 0.0,
+                 krylov_path: int = 0):
         import torch
         self.wl = wl
         self.rmax = wl.rmax if rmax is None else rmax
@@ -86,7 +88,8 @@ class KeffSolver:
                                     max_sweeps=max_sweeps, rhs_mode=rhs_mode,
                                     rhs_rmax=rhs_rmax, direct_max=direct_max,
                                     gmres_restart=gmres_restart, precision=precision,
-                                    min_sweeps=min_sweeps, cap_eta=cap_eta, stall=stall)
+                                    min_sweeps=min_sweeps, cap_eta=cap_eta, stall=stall,
+                                    krylov_path=krylov_path)
         self.history: List[StepRecord] = []
 
     @property
@@ -132,3 +135,54 @@ def step_batched(solvers: List["KeffSolver"], streams) -> List[StepRecord]:
         s.history.append(rec)
         recs.append(rec)
     return recs
+
+
+class AlphaSolver:
+    """Alpha-eigenvalue outer iteration (eq. alpha_eig_fixed_points) on the device.
+
+    The alpha V^{-1} term of eq. OpFormAlphaNTE enters the cell equation
+    (eq. Discretized_alphaNTE) with the same 8-vertex average as the total
+    cross section, so H(alpha) is the transport operator built with
+    sigma_t + alpha / v_g.  Each outer step runs the k power iteration of
+    H(alpha) psi = (S + F / k) psi to convergence with tt_power_step (the
+    previous alpha's flux as the start); alpha starts at 0 and 0.01 and is
+    updated by the secant step on k(alpha) = 1.
+    """
+
+    def __init__(self, wl, inv_v, alpha0: float = 0.0, alpha1: float = 0.01, **solver_kw):
+        self.wl = wl
+        self.inv_v = np.asarray(inv_v, dtype=np.float64)
+        assert self.inv_v.shape == (wl.G,)
+        self.alpha0, self.alpha1 = float(alpha0), float(alpha1)
+        self.solver_kw = solver_kw
+        self.history: List[tuple] = []     # (alpha, k, power steps)
+
+    def k_of_alpha(self, alpha: float, max_steps: int, tol_k: float, psi0=None) -> tuple:
+        w = dataclasses.replace(self.wl, sigma_t=self.wl.sigma_t + alpha * self.inv_v[None, :])
+        ops = operators.build(w)
+        if psi0 is not None:
+            ops.psi0 = psi0
+        s = KeffSolver(w, ops=ops, **self.solver_kw)
+        s.run(max_steps=max_steps, tol_k=tol_k)
+        rec = (alpha, s.k, len(s.history))
+        psi = [c.copy() for c in s.psi_cores()]
+        s.close()
+        return rec, psi
+
+    def run(self, tol_alpha: float = 1e-8, tol_k: float = 1e-10, max_outer: int = 30,
+            max_steps: int = 400) -> float:
+        r0, psi = self.k_of_alpha(self.alpha0, max_steps, tol_k)
+        r1, psi = self.k_of_alpha(self.alpha1, max_steps, tol_k, psi)
+        self.history = [r0, r1]
+        (a_prev, k_prev, _), (a, k, _) = r0, r1
+        for _ in range(max_outer):
+            if k == k_prev:
+                break
+            a_next = a + (1.0 - k) * (a - a_prev) / (k - k_prev)
+            rec, psi = self.k_of_alpha(a_next, max_steps, tol_k, psi)
+            self.history.append(rec)
+            done = abs(a_next - a) <= tol_alpha * max(1.0, abs(a_next))
+            a_prev, k_prev, a, k = a, k, a_next, rec[1]
+            if done:
+                break
+        return a

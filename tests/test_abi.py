@@ -157,3 +157,13 @@ def test_noalloc_local_solve_rejects_systems_above_its_scratch():
                                     ctypes.byref(info), None)
     assert st == native.TT_E_CAPACITY
     assert b"static scratch" in lib.tt_last_error()
+
+
+def test_local_apply_validates_before_launch():
+    lib = native.lib()
+    fake = ctypes.c_void_p(0x1000)
+    sysd = native.TTLocal(3, 2, 2, 2, 2, 3, fake, fake, fake, None)
+    ws = lib.tt_local_apply_workspace(ctypes.byref(sysd))
+    assert ws > 0
+    assert lib.tt_local_apply(ctypes.byref(sysd), fake, fake, 1, fake, ws, None) == native.TT_E_ARG
+    assert lib.tt_local_apply(ctypes.byref(sysd), fake, fake, 0, fake, 8, None) == native.TT_E_CAPACITY
