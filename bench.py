@@ -373,12 +373,14 @@ def main():
         small = W.config(0)
         ttk_small = dict(workload="homogeneous_n8_S2, rank cap 64 (tol 1e-10 governs)",
                          fp64=_time_to_k(small, 64, args.rhs_mode, 100),
-                         mixed=_time_to_k(small, 64, args.rhs_mode, 100, precision=1))
+                         mixed=_time_to_k(small, 64, args.rhs_mode, 100, precision=2))
 
     mixed = None
     if not args.no_mixed:
-        # the same workload with FP32 Arnoldi cycles refining FP64 local residuals
-        sm = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode, ops=s.ops, precision=1)
+        # the same workload in the mixed mode: local GMRES cycles on FP32 (persistent
+        # kernel) or with BF16 matrix-core products (multi-launch GMRES), each cycle
+        # refining the FP64 local residual
+        sm = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode, ops=s.ops, precision=2)
         for _ in range(args.warmup):
             sm.step()
         torch.cuda.synchronize()
@@ -394,7 +396,9 @@ def main():
                      k_rel_diff_vs_fp64=abs(hm[-1].k - hist[len(hm) - 1].k) / abs(hist[len(hm) - 1].k),
                      local_iters_last=hm[-1].local_iters,
                      fp64_local_iters_last=hist[len(hm) - 1].local_iters,
-                     dtype="f32 Krylov cycles, f64 residuals / QR / SVD / k")
+                     dtype="bf16 matrix-core products (fp32 accumulation) and fp32 Krylov "
+                           "cycles in refined local solves; fp64 residuals, interfaces, "
+                           "QR / SVD, k")
         sm.close()
 
     cpu = None

@@ -224,6 +224,15 @@ tt_status tt_local_solve_noalloc(const tt_local* sys, double* x, const tt_solve_
 tt_status ttnt_set_grid_wait_limit(double seconds);
 
 /*
+ * ttnt_release - waits for the device, then frees the HIP event and pinned
+ * host buffer that the blocking calls (tt_round and the other calls that read
+ * ranks back) keep for the calling thread.  For an orderly teardown before
+ * the process ends (every tt_solver should be destroyed first); later calls
+ * recreate what they need.
+ */
+tt_status ttnt_release(void);
+
+/*
  * Power-iteration solver (one call of tt_power_step = one step of
  * eq. TT_k_eff_fixed_points).
  *

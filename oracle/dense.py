@@ -53,17 +53,21 @@ def _node(n, k, j, i):
 def equation_operators(wl, periodic=None):
     """H, S, F (CSR) in the equation-row arrangement, unknowns psi[g,l,k,j,i].
 
-    ``periodic`` (per axis z, y, x; default: ``wl.periodic``) replaces the
-    vacuum row psi = 0 of an incoming-face node on that axis by
+    Node counts and spacings may differ per axis (the cell equation carries
+    Delta x_i, Delta y_j, Delta z_k).  ``periodic`` (per axis z, y, x;
+    default: ``wl.periodic``) replaces the vacuum row psi = 0 of an
+    incoming-face node on that axis by
     psi(node) - psi(node on the opposite face) = 0.  A node on several
     incoming faces takes the condition of the x face first, then y, then z.
     """
-    n, M, h = _grid(wl)
+    nz, ny, nx = (wl.axis_nodes(ax) for ax in range(3))
+    hz, hy, hx = (wl.axis_spacing(ax) for ax in range(3))
     G, L = wl.G, wl.L
     if periodic is None:
         periodic = getattr(wl, "periodic", (False, False, False))
     per_z, per_y, per_x = (bool(p) for p in periodic)
-    N = n ** 3
+    N = nz * ny * nx
+    node = lambda k, j, i: (k * ny + j) * nx + i
     mat = wl.cell_material()
     q = wl.quad
     Hr, Hc, Hv = [], [], []
@@ -73,56 +77,63 @@ def equation_operators(wl, periodic=None):
         for l in range(L):
             base = (g * L + l) * N
             mu, eta, xi = q.mu[l], q.eta[l], q.xi[l]
-            i_in = 0 if mu > 0 else n - 1
-            j_in = 0 if eta > 0 else n - 1
-            k_in = 0 if xi > 0 else n - 1
-            for k in range(n):
-                for j in range(n):
-                    for i in range(n):
+            i_in = 0 if mu > 0 else nx - 1
+            j_in = 0 if eta > 0 else ny - 1
+            k_in = 0 if xi > 0 else nz - 1
+            for k in range(nz):
+                for j in range(ny):
+                    for i in range(nx):
                         if i == i_in or j == j_in or k == k_in:
-                            r = base + _node(n, k, j, i)
+                            r = base + node(k, j, i)
                             Hr.append(r); Hc.append(r); Hv.append(1.0)
                             if i == i_in:
-                                opp = _node(n, k, j, n - 1 - i) if per_x else None
+                                opp = node(k, j, nx - 1 - i) if per_x else None
                             elif j == j_in:
-                                opp = _node(n, k, n - 1 - j, i) if per_y else None
+                                opp = node(k, ny - 1 - j, i) if per_y else None
                             else:
-                                opp = _node(n, n - 1 - k, j, i) if per_z else None
+                                opp = node(nz - 1 - k, j, i) if per_z else None
                             if opp is not None:
                                 Hr.append(r); Hc.append(base + opp); Hv.append(-1.0)
-            for ck in range(1, n):
-                for cj in range(1, n):
-                    for ci in range(1, n):
-                        ok = ck if xi > 0 else ck - 1
-                        oj = cj if eta > 0 else cj - 1
-                        oi = ci if mu > 0 else ci - 1
-                        r = base + _node(n, ok, oj, oi)
-                        m = mat[ck - 1, cj - 1, ci - 1]
-                        st = wl.sigma_t[m, g]
-                        for kk in (ck - 1, ck):
-                            for jj in (cj - 1, cj):
-                                for ii in (ci - 1, ci):
-                                    c = base + _node(n, kk, jj, ii)
-                                    v = st / 8.0
-                                    v += mu / (4 * h) * (1.0 if ii == ci else -1.0)
-                                    v += eta / (4 * h) * (1.0 if jj == cj else -1.0)
-                                    v += xi / (4 * h) * (1.0 if kk == ck else -1.0)
-                                    Hr.append(r); Hc.append(c); Hv.append(v)
-                        for gp in range(G):
-                            ss = wl.sigma_s[m, g, gp] / 8.0
-                            ff = wl.chi[g] * wl.nu_sigma_f[m, gp] / 8.0
-                            for lp in range(L):
-                                cb = (gp * L + lp) * N
-                                for kk in (ck - 1, ck):
-                                    for jj in (cj - 1, cj):
-                                        for ii in (ci - 1, ci):
-                                            c = cb + _node(n, kk, jj, ii)
-                                            if ss != 0.0:
-                                                Sr.append(r); Sc.append(c); Sv.append(ss * q.w[lp])
-                                            if ff != 0.0:
-                                                Fr.append(r); Fc.append(c); Fv.append(ff * q.w[lp])
+            # cell equations, all cells of this (g, l) at once; cell c = (ck, cj, ci)
+            # (1-based) sits at the row of its outgoing vertex
+            ck, cj, ci = np.meshgrid(np.arange(1, nz), np.arange(1, ny), np.arange(1, nx),
+                                     indexing="ij")
+            ck, cj, ci = ck.ravel(), cj.ravel(), ci.ravel()
+            ok = ck if xi > 0 else ck - 1
+            oj = cj if eta > 0 else cj - 1
+            oi = ci if mu > 0 else ci - 1
+            rows = base + node(ok, oj, oi)
+            m = mat[ck - 1, cj - 1, ci - 1]
+            st = wl.sigma_t[m, g]
+            verts = [(kk, jj, ii) for kk in (0, 1) for jj in (0, 1) for ii in (0, 1)]
+            for dk, dj, di in verts:
+                # vertex (ck - 1 + dk, cj - 1 + dj, ci - 1 + di)
+                cols = base + node(ck - 1 + dk, cj - 1 + dj, ci - 1 + di)
+                v = st / 8.0
+                v = v + mu / (4 * hx) * (1.0 if di else -1.0)
+                v = v + eta / (4 * hy) * (1.0 if dj else -1.0)
+                v = v + xi / (4 * hz) * (1.0 if dk else -1.0)
+                Hr.append(rows); Hc.append(cols); Hv.append(np.broadcast_to(v, rows.shape))
+            for gp in range(G):
+                ss = wl.sigma_s[m, g, gp] / 8.0
+                ff = wl.chi[g] * wl.nu_sigma_f[m, gp] / 8.0
+                for dk, dj, di in verts:
+                    vnode = node(ck - 1 + dk, cj - 1 + dj, ci - 1 + di)
+                    for lp in range(L):
+                        cols = (gp * L + lp) * N + vnode
+                        if np.any(ss != 0.0):
+                            Sr.append(rows); Sc.append(cols); Sv.append(ss * q.w[lp])
+                        if np.any(ff != 0.0):
+                            Fr.append(rows); Fc.append(cols); Fv.append(ff * q.w[lp])
     T = G * L * N
-    mk = lambda r, c, v: sp.csr_matrix((v, (r, c)), shape=(T, T))
+    def mk(r, c, v):
+        if not r:
+            return sp.csr_matrix((T, T))
+        rr = np.concatenate([np.atleast_1d(x).ravel() for x in r]).astype(np.int64)
+        cc = np.concatenate([np.atleast_1d(x).ravel() for x in c]).astype(np.int64)
+        vv = np.concatenate([np.broadcast_to(np.asarray(x, dtype=float), np.shape(np.atleast_1d(rx))).ravel()
+                             for x, rx in zip(v, r)])
+        return sp.csr_matrix((vv, (rr, cc)), shape=(T, T))
     return mk(Hr, Hc, Hv), mk(Sr, Sc, Sv), mk(Fr, Fc, Fv)
 
 

@@ -117,13 +117,13 @@ class Problem:
 
     @classmethod
     def from_workload(cls, wl, reflective=None):
-        n = wl.n
-        h = 1.0 / (n - 1)
+        shape = tuple(wl.axis_nodes(ax) for ax in range(3))
+        spacing = tuple(wl.axis_spacing(ax) for ax in range(3))
         if reflective is None:
             reflective = (wl.boundary == "reflective",) * 3
         q = wl.quad
         return cls(wl.G, q.mu, q.eta, q.xi, q.w, wl.cell_material(), wl.sigma_t,
-                   wl.sigma_s, wl.nu_sigma_f, wl.chi, (n, n, n), (h, h, h), reflective)
+                   wl.sigma_s, wl.nu_sigma_f, wl.chi, shape, spacing, reflective)
 
     @property
     def n_unknowns(self) -> int:
@@ -185,7 +185,7 @@ def dense_psi0(wl) -> np.ndarray:
     axes = []
     for ax in range(3):
         v = np.ones(1)
-        for b in range(wl.l):
+        for b in range(wl.axis_bits(ax)):
             v = np.kron(v, wl.psi0_bits[ax, b])
         axes.append(v)
     e = wl.psi0_energy if wl.G > 1 else np.ones(1)

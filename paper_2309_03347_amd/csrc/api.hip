@@ -328,6 +328,13 @@ tt_status tt_local_solve_noalloc(const tt_local* sys, double* x, const tt_solve_
   });
 }
 
+tt_status ttnt_release(void) {
+  return guard([&] {
+    TT_HIP(hipDeviceSynchronize());
+    release_thread_resources();
+  });
+}
+
 tt_status ttnt_set_grid_wait_limit(double seconds) {
   return guard([&] {
     TT_REQUIRE(seconds == seconds, "seconds is NaN");

@@ -67,6 +67,9 @@ struct HostBuf {
 // skipped.
 Co round_tt_co(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws,
                SyncSlot& slot, HostBuf hb, bool left_orth = false);
+// Frees the calling thread's event and pinned buffer used by blocking calls
+// (recreated on the next such call).
+void release_thread_resources();
 // Blocking form of round_tt_co (synchronizes the stream).
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws);
 size_t round_ws_bytes(const TTv& x);

@@ -122,26 +122,34 @@ size_t round_ws_bytes(const TTv& x) {
 }
 
 namespace {
-// Event and pinned scratch for blocking calls made by one host thread (kept
-// for the life of the process).
+// Event and pinned scratch for blocking calls made by one host thread, kept
+// until release_thread_resources() (or the end of the process).
 struct BlockingCtx {
   SyncSlot slot;
   HostBuf hb{nullptr, nullptr};
 };
+thread_local BlockingCtx* t_blocking = nullptr;
 BlockingCtx& blocking_ctx() {
-  thread_local BlockingCtx* c = nullptr;
-  if (!c) {
+  if (!t_blocking) {
     auto* n = new BlockingCtx();
     TT_HIP(hipEventCreateWithFlags(&n->slot.ev, hipEventDisableTiming));
     void* p = nullptr;
     TT_HIP(hipHostMalloc(&p, 256, hipHostMallocDefault));
     n->hb.i = static_cast<int*>(p);
     n->hb.d = reinterpret_cast<double*>(static_cast<char*>(p) + 64);
-    c = n;
+    t_blocking = n;
   }
-  return *c;
+  return *t_blocking;
 }
 }  // namespace
+
+void release_thread_resources() {
+  if (!t_blocking) return;
+  if (t_blocking->slot.ev) (void)hipEventDestroy(t_blocking->slot.ev);
+  if (t_blocking->hb.i) (void)hipHostFree(t_blocking->hb.i);
+  delete t_blocking;
+  t_blocking = nullptr;
+}
 
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws) {
   BlockingCtx& c = blocking_ctx();

@@ -26,7 +26,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
-            "tt_local_apply"]
+            "tt_local_apply", "ttnt_release"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -136,6 +136,7 @@ def lib():
                                              ctypes.POINTER(TTSolveInfo), v]
         L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
         L.tt_orth_right.argtypes = [ctypes.POINTER(TTVec), v, ctypes.c_size_t, v]
+        L.ttnt_release.argtypes = []
         L.tt_local_apply_workspace.argtypes = [ctypes.POINTER(TTLocal)]
         L.tt_local_apply_workspace.restype = ctypes.c_size_t
         L.tt_local_apply.argtypes = [ctypes.POINTER(TTLocal), v, v, ctypes.c_int32, v,
@@ -363,6 +364,13 @@ def tt_local_solve_noalloc(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1
     torch.cuda.synchronize()
     return x, dict(iterations=info.iterations, method=info.method_used, rel_res=info.rel_res,
                    converged=st == TT_OK)
+
+
+def release() -> None:
+    """Orderly teardown: wait for the device and free the library's per-thread
+    event and pinned buffer (destroy every Solver first)."""
+    if _lib is not None:
+        _check(_lib.ttnt_release())
 
 
 def set_grid_wait_limit(seconds: float) -> None:

@@ -92,7 +92,8 @@ def _row_intervals(wl, ax, pos):
     Row i holds the equation of cell i (pos) or cell i+1 (neg); the face row
     (0 for pos, n-1 for neg) joins the block of the adjacent cell.
     """
-    n, M = wl.n, wl.M
+    n = wl.axis_nodes(ax)
+    M = n - 1
     out = []
     for lo, hi in wl.block_intervals(ax):
         if pos:
@@ -120,7 +121,7 @@ def _material_term(wl, o, energy_mats: np.ndarray, no_bc: bool,
     factor is C_o (x) I for H (no_bc False, or ``collision``) or Intg^o for
     S, F (no_bc True).
     """
-    G, L, l = wl.G, wl.L, wl.l
+    G, L = wl.G, wl.L
     per = L // 8
     sel = np.zeros(L)
     sel[o * per:(o + 1) * per] = 1.0
@@ -142,6 +143,7 @@ def _material_term(wl, o, energy_mats: np.ndarray, no_bc: bool,
     signs = _octant_signs(o)
     for ax, c in zip((0, 1, 2), (cz, cy, cx)):
         pos = signs[2 - ax]                  # axis 0 is z (sign bit 4), 2 is x (bit 1)
+        l = wl.axis_bits(ax)
         P = _interp(l, pos, no_bc)
         blocks = []
         for (a, b) in _row_intervals(wl, ax, pos):
@@ -164,14 +166,15 @@ def _energy_angle(wl, Qdiag) -> Cores:
 
 def octant_terms(wl, o):
     """The streaming and collision terms of H for one octant (list of TTs)."""
-    l, h = wl.l, 1.0 / (wl.n - 1)
+    lz, ly, lx = (wl.axis_bits(ax) for ax in range(3))
+    hz, hy, hx = (wl.axis_spacing(ax) for ax in range(3))
     px, py, pz = _octant_signs(o)
     per = wl.L // 8
     sel = np.zeros(wl.L)
     sel[o * per:(o + 1) * per] = 1.0
     q = wl.quad
-    Ix, Iy, Iz = _interp(l, px), _interp(l, py), _interp(l, pz)
-    Dx, Dy, Dz = _diff(l, h, px), _diff(l, h, py), _diff(l, h, pz)
+    Ix, Iy, Iz = _interp(lx, px), _interp(ly, py), _interp(lz, pz)
+    Dx, Dy, Dz = _diff(lx, hx, px), _diff(ly, hy, py), _diff(lz, hz, pz)
     terms = [
         qtt.kron_chain([_energy_angle(wl, sel * q.mu), Iz, Iy, Dx]),
         qtt.kron_chain([_energy_angle(wl, sel * q.eta), Iz, Dy, Ix]),
@@ -192,25 +195,26 @@ def octant_terms_explicit_faces(wl, o):
     solutions as ``octant_terms``, whose face rows are a two-dimensional
     transport problem with no source.
     """
-    l, h = wl.l, 1.0 / (wl.n - 1)
+    lz, ly, lx = (wl.axis_bits(ax) for ax in range(3))
+    hz, hy, hx = (wl.axis_spacing(ax) for ax in range(3))
     px, py, pz = _octant_signs(o)
     per_z, per_y, per_x = (bool(p) for p in wl.periodic)
     per = wl.L // 8
     sel = np.zeros(wl.L)
     sel[o * per:(o + 1) * per] = 1.0
     q = wl.quad
-    Ix, Iy, Iz = (_interp(l, p, True) for p in (px, py, pz))
-    Dx, Dy, Dz = (_diff_nobc(l, h, p) for p in (px, py, pz))
-    Px, Py = _row_projector(l, px), _row_projector(l, py)
-    E = qtt.qtt_eye(l)
+    Ix, Iy, Iz = _interp(lx, px, True), _interp(ly, py, True), _interp(lz, pz, True)
+    Dx, Dy, Dz = _diff_nobc(lx, hx, px), _diff_nobc(ly, hy, py), _diff_nobc(lz, hz, pz)
+    Px, Py = _row_projector(lx, px), _row_projector(ly, py)
+    Ey, Ez = qtt.qtt_eye(ly), qtt.qtt_eye(lz)
     return [
         qtt.kron_chain([_energy_angle(wl, sel * q.mu), Iz, Iy, Dx]),
         qtt.kron_chain([_energy_angle(wl, sel * q.eta), Iz, Dy, Ix]),
         qtt.kron_chain([_energy_angle(wl, sel * q.xi), Dz, Iy, Ix]),
         _material_term(wl, o, np.stack([np.diag(s) for s in wl.sigma_t]), True, collision=True),
-        qtt.kron_chain([_energy_angle(wl, sel), E, E, _face_rows(l, h, px, per_x)]),
-        qtt.kron_chain([_energy_angle(wl, sel), E, _face_rows(l, h, py, per_y), Px]),
-        qtt.kron_chain([_energy_angle(wl, sel), _face_rows(l, h, pz, per_z), Py, Px]),
+        qtt.kron_chain([_energy_angle(wl, sel), Ez, Ey, _face_rows(lx, hx, px, per_x)]),
+        qtt.kron_chain([_energy_angle(wl, sel), Ez, _face_rows(ly, hy, py, per_y), Px]),
+        qtt.kron_chain([_energy_angle(wl, sel), _face_rows(lz, hz, pz, per_z), Py, Px]),
     ]
 
 
@@ -279,7 +283,7 @@ def build(wl, tol: float = 1e-13) -> Operators:
         psi0.append(wl.psi0_energy.reshape(1, -1, 1).copy())
     psi0.append(wl.psi0_angle.reshape(1, -1, 1).copy())
     for ax in range(3):
-        for b in range(wl.l):
+        for b in range(wl.axis_bits(ax)):
             psi0.append(wl.psi0_bits[ax, b].reshape(1, 2, 1).copy())
     modes = [c.shape[1] for c in psi0]
     return Operators(H, S, F, cF, psi0, modes)

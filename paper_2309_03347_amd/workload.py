@@ -77,6 +77,8 @@ class Workload:
     seed: int
     boundary: str = "vacuum"    # "vacuum", or "reflective" (lagged mirror faces, sweep checker only)
     periodic: tuple = (False, False, False)   # per axis (z, y, x): inflow face = opposite face
+    l_axes: Optional[tuple] = None            # per axis (z, y, x) bits; None: l on every axis
+    lengths: tuple = (1.0, 1.0, 1.0)          # per axis (z, y, x) extent of the box
 
     @property
     def n(self) -> int:
@@ -90,12 +92,30 @@ class Workload:
     def L(self) -> int:
         return self.quad.L
 
+    def axis_bits(self, ax: int) -> int:
+        return self.l if self.l_axes is None else int(self.l_axes[ax])
+
+    def axis_nodes(self, ax: int) -> int:
+        return 1 << self.axis_bits(ax)
+
+    def axis_spacing(self, ax: int) -> float:
+        return float(self.lengths[ax]) / (self.axis_nodes(ax) - 1)
+
+    @property
+    def shape(self):
+        """Node counts per axis (z, y, x)."""
+        return tuple(self.axis_nodes(ax) for ax in range(3))
+
+    @property
+    def n_nodes(self) -> int:
+        nz, ny, nx = self.shape
+        return nz * ny * nx
+
     def cell_material(self) -> np.ndarray:
-        """Material id of every cell, int array [M, M, M] indexed (cz-1, cy-1, cx-1)."""
-        M = self.M
+        """Material id of every cell, int array [Mz, My, Mx] indexed (cz-1, cy-1, cx-1)."""
         idx = []
         for ax in range(3):
-            b = np.zeros(M, dtype=np.int64)
+            b = np.zeros(self.axis_nodes(ax) - 1, dtype=np.int64)
             for c in self.cuts[ax]:
                 b[c - 1:] += 1
             idx.append(b)
@@ -104,7 +124,7 @@ class Workload:
     def block_intervals(self, ax: int):
         """Inclusive 1-based cell interval of every block along axis ``ax``."""
         starts = [1] + list(self.cuts[ax])
-        ends = [s - 1 for s in self.cuts[ax]] + [self.M]
+        ends = [s - 1 for s in self.cuts[ax]] + [self.axis_nodes(ax) - 1]
         return list(zip(starts, ends))
 
 
@@ -262,6 +282,48 @@ def checkerboard(l: int = 7, G: int = 8, N: int = 8, blocks: int = 4,
         cuts=cuts, block_mat=block_mat.astype(np.int64), sigma_t=st,
         sigma_s=ss, nu_sigma_f=nf, chi=chi, psi0_energy=e, psi0_angle=a,
         psi0_bits=bits, rmax=rmax, tol=tol, tol_k=tol_k, seed=seed)
+
+
+def gauss_legendre_slab(N: int) -> Quadrature:
+    """Ordinates for a slab along x: the N-point Gauss-Legendre cosines mu
+    (weights normalized to 1/8 per octant), with eta = xi = sqrt((1 - mu^2)/2)
+    so that each direction is a unit vector; the y and z cosines do not enter
+    a solution that is uniform in y and z."""
+    mu_gl, w_gl = np.polynomial.legendre.leggauss(N)
+    pos = mu_gl > 0
+    mu_m, w_m = mu_gl[pos], w_gl[pos] / w_gl[pos].sum()
+    per = mu_m.size
+    tr = np.sqrt((1.0 - mu_m ** 2) / 2.0)
+    L = 8 * per
+    mu, eta, xi, w = (np.empty(L) for _ in range(4))
+    for o in range(8):
+        sl = slice(o * per, (o + 1) * per)
+        mu[sl] = (1.0 if o & 1 else -1.0) * mu_m
+        eta[sl] = (1.0 if o & 2 else -1.0) * tr
+        xi[sl] = (1.0 if o & 4 else -1.0) * tr
+        w[sl] = w_m / 8.0
+    return Quadrature(mu, eta, xi, w)
+
+
+def slab(N: int, lx: int, sigma_t: float, sigma_s: float, nu_sigma_f: float, width: float,
+         seed: int = 0, rmax: int = 32, tol: float = 1e-10, tol_k: float = 1e-10,
+         name: Optional[str] = None) -> Workload:
+    """One-group homogeneous slab of the given width along x (vacuum faces),
+    2^lx nodes across it; y and z have two nodes and periodic faces, so the
+    solution is uniform in y and z (a one-dimensional slab)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    quad = gauss_legendre_slab(N)
+    a = rng.uniform(0.5, 1.5, size=quad.L)
+    bits = np.ones((3, lx, 2))
+    bits[2] = rng.uniform(0.5, 1.5, size=(lx, 2))
+    return Workload(
+        name=name or f"slab_nx{1 << lx}_S{N}", l=lx, G=1, quad=quad,
+        cuts=[[], [], []], block_mat=np.zeros((1, 1, 1), dtype=np.int64),
+        sigma_t=np.array([[sigma_t]]), sigma_s=np.array([[[sigma_s]]]),
+        nu_sigma_f=np.array([[nu_sigma_f]]), chi=np.ones(1),
+        psi0_energy=np.ones(1), psi0_angle=a, psi0_bits=bits, rmax=rmax, tol=tol,
+        tol_k=tol_k, seed=seed, periodic=(True, True, False), l_axes=(1, 1, lx),
+        lengths=(1.0, 1.0, float(width)))
 
 
 def config(idx: int, **over) -> Workload:

@@ -32,10 +32,10 @@ def test_alpha_periodic_infinite_medium_closed_form(cuda):
     from paper_2309_03347_amd.solver import AlphaSolver
     wl = W.homogeneous(l=5, N=4, seed=42, tol=1e-10, rmax=16)
     wl.periodic = (True, True, True)
-    st, ss, nf = wl.sigma_t[0, 0], wl.sigma_s[0, 0], wl.nu_sigma_f[0, 0]
+    st, ss, nf = wl.sigma_t[0, 0], wl.sigma_s[0, 0, 0], wl.nu_sigma_f[0, 0]
     inv_v = np.array([0.5])
     sol = AlphaSolver(wl, inv_v)
     a = sol.run(tol_alpha=1e-10, tol_k=1e-12)
-    exact = (nf + ss - st) / inv_v[0]
+    exact = float((nf + ss - st) / inv_v[0])
     print(f"alpha {a:.12f} closed form {exact:.12f}", flush=True)
     assert abs(a - exact) <= 1e-8

@@ -78,3 +78,28 @@ def test_periodic_infinite_medium_k_closed_form(cuda, l, G, N):
     # the converged flux is the constant, a rank-1 train
     assert rec.max_rank <= 2, rec.max_rank
     s.close()
+
+
+def test_pu239_slab_on_device_tends_to_critical(cuda):
+    # The one-dimensional Pu-239 slab of Table tab:1dbench (exactly critical):
+    # 256 nodes across 3.707 cm, two nodes with periodic faces in y and z,
+    # Gauss-Legendre S4, S8, S16.  The device k equals the checker's dense
+    # eigenvalue of the same operator and tends to 1 as the ordinate count grows.
+    import json
+    import os
+    from paper_2309_03347_amd.solver import KeffSolver
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pu239_slab.json")))
+    errs = []
+    for N in (4, 8, 16):
+        wl = W.slab(N, 8, d["sigma_t"], d["sigma_s"], d["nu"] * d["sigma_f"], d["width_cm"],
+                    rmax=32, tol=1e-10, tol_k=1e-12)
+        H, S, F = dense.equation_operators(wl)
+        k_ref = dense.k_dominant(H, S, F)
+        s = KeffSolver(wl)
+        s.run(max_steps=200, tol_k=1e-12)
+        print(f"slab S{N}: device k {s.k:.12f} checker {k_ref:.12f} steps {len(s.history)}",
+              flush=True)
+        assert abs(s.k - k_ref) <= 1e-8 * k_ref
+        errs.append(abs(1.0 - s.k))
+        s.close()
+    assert errs[0] > errs[1] > errs[2]
