@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks used for the roofline fraction
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
 
 # HBM bytes per launch of a kernel class from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain copy (profiles/gmres_slices_inner_box_n32_G4_S4_traffic.md),
@@ -96,6 +97,9 @@ def _parse():
     p.add_argument("--largest-steps", type=int, default=2,
                    help="timed steps of the largest configuration (0 skips it)")
     p.add_argument("--largest-warmup", type=int, default=1)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only copy a 256 MiB float64 device buffer three times (the plain "
+                        "copy that scales the HBM traffic counters) and exit")
     return p.parse_args()
 
 
@@ -205,6 +209,31 @@ def _build_ops(w):
     return operators.build(w)
 
 
+def _roofline(probe, workload):
+    """Roofline of the dominant kernel class (by total device time) of a probe."""
+    name, st = max(probe.items(), key=lambda kv: kv[1]["total_ms"])
+    if st["launches"] == 0:
+        return None
+    avg_ms = st["total_ms"] / st["launches"]
+    # bound by arithmetic intensity against the ridge of the class's arithmetic
+    peak_tf = PEAK_BF16_TFLOPS if name == "gemm_bf16" else PEAK_FP64_TFLOPS
+    ridge = peak_tf * 1e12 / (PEAK_HBM_GBS * 1e9)
+    intensity = st["flops"] / max(1.0, st["bytes"])
+    if intensity >= ridge:
+        achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
+        out = dict(bound="mfma" if name == "gemm_bf16" else "alu", achieved=achieved,
+                   peak=peak_tf, unit="TFLOP/s", frac=achieved / peak_tf)
+    else:
+        achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
+        out = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                   frac=achieved / PEAK_HBM_GBS)
+    out["traffic"] = _measured_traffic(name, workload)
+    out.update(kernel=name, intensity_flop_per_byte=intensity, launches=st["launches"],
+               avg_us=avg_ms * 1e3, flops_per_launch=st["flops"] / st["launches"],
+               bytes_per_launch=st["bytes"] / st["launches"])
+    return out
+
+
 def _bench_batch(args):
     """Many uneven instances advanced by tt_power_step_batched."""
     import concurrent.futures as cf
@@ -234,6 +263,22 @@ def _bench_batch(args):
         print(f"timed batched step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # kernel probe over one more batched step: every solver's launches of the
+    # timed classes bracketed by HIP events on its own stream
+    roofline = None
+    if not args.no_probe:
+        for sv in solvers:
+            sv.native.set_probe(True)
+        step_batched(solvers, streams)
+        torch.cuda.synchronize()
+        tot = {}
+        for sv in solvers:
+            for name, st in sv.native.probe_stats().items():
+                acc = tot.setdefault(name, dict(launches=0, total_ms=0.0, flops=0.0, bytes=0.0))
+                for key in acc:
+                    acc[key] += st[key]
+            sv.native.set_probe(False)
+        roofline = _roofline(tot, "batch256_uneven")
     cpu = None
     if not args.no_cpu_baseline:
         import numpy as np
@@ -262,13 +307,14 @@ def _bench_batch(args):
                    "instances": len(solvers), "streams": args.streams,
                    "setup_seconds": setup},
         "max_rank": int(max(max(s.native.ranks()) for s in solvers)),
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     for s in solvers:
         s.close()
     print("solvers closed", file=sys.stderr, flush=True)
+    _teardown()
 
 
 def _largest(args):
@@ -313,6 +359,15 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the batch and "
               "single-instance paths are single-device by design.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("copied 3 x 256 MiB", flush=True)
+        return
     if args.workload == "batch256_uneven":
         return _bench_batch(args)
     import numpy as np
@@ -344,25 +399,7 @@ def main():
         torch.cuda.synchronize()
         probe = s.native.probe_stats()
         s.native.set_probe(False)
-        # dominant kernel class by total device time
-        name, st = max(probe.items(), key=lambda kv: kv[1]["total_ms"])
-        avg_ms = st["total_ms"] / max(1, st["launches"])
-        # bound by arithmetic intensity against the FP64 ridge (peak flops / HBM bandwidth)
-        ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-        intensity = st["flops"] / max(1.0, st["bytes"])
-        if intensity >= ridge:
-            achieved = st["flops"] / (st["total_ms"] * 1e-3) / 1e12
-            roofline = dict(bound="alu", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                            frac=achieved / PEAK_FP64_TFLOPS, traffic=None)
-        else:
-            achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
-            roofline = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                            frac=achieved / PEAK_HBM_GBS, traffic=None)
-        roofline["traffic"] = _measured_traffic(name, args.workload)
-        roofline.update(kernel=name, intensity_flop_per_byte=intensity,
-                        launches=st["launches"], avg_us=avg_ms * 1e3,
-                        flops_per_launch=st["flops"] / max(1, st["launches"]),
-                        bytes_per_launch=st["bytes"] / max(1, st["launches"]))
+        roofline = _roofline(probe, args.workload)
 
     ttk = ttk_small = None
     if args.ttk_steps > 0:
@@ -374,6 +411,8 @@ def main():
         ttk_small = dict(workload="homogeneous_n8_S2, rank cap 64 (tol 1e-10 governs)",
                          fp64=_time_to_k(small, 64, args.rhs_mode, 100),
                          mixed=_time_to_k(small, 64, args.rhs_mode, 100, precision=2))
+        ttk_small["mixed_k_rel_diff_vs_fp64"] = abs(ttk_small["mixed"]["k_ref"] -
+                                                    ttk_small["fp64"]["k_ref"]) / ttk_small["fp64"]["k_ref"]
 
     mixed = None
     if not args.no_mixed:
@@ -440,8 +479,18 @@ def main():
     if probe is not None:
         out["kernel_probe"] = {k: dict(launches=v["launches"], ms=round(v["total_ms"], 3))
                                for k, v in probe.items() if v["launches"]}
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
     s.close()
+    _teardown()
+
+
+def _teardown():
+    """Orderly end: wait for the device and free the library's per-thread
+    resources before the interpreter and the HIP runtime shut down."""
+    import torch
+    from paper_2309_03347_amd import native
+    torch.cuda.synchronize()
+    native.release()
 
 
 if __name__ == "__main__":

@@ -309,6 +309,24 @@ tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts
                            tt_solver** out);
 tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);
 /*
+ * tt_amen_mv - approximate TT matrix-vector product y ~ A x with y's ranks
+ * chosen by the alternating sweeps (the amen_mv route named in Section 3.3,
+ * eq. mv_obj): the sweeps of tt_power_step with the identity in place of H,
+ * so each local problem is the projection of A x onto the current left and
+ * right orthonormal interfaces, followed by the residual enrichment and the
+ * final rounding to (tol, rmax).  Unlike tt_matvec the product's ranks never
+ * reach R_k r_k.  A square in every mode; x and y modes equal A's.  Writes
+ * y->r; TT_E_CAPACITY if y's capacity is below the ranks found (nothing
+ * written to y).  info (host, may be NULL) receives sweeps, the largest
+ * local change before a sweep (max_local_res), the final truncation error
+ * and the ranks; TT_E_NOCONV when max_sweeps ended the sweeps above tol (y
+ * still written).  Allocates its own device scratch (like
+ * tt_solver_create).  Synchronizes `stream`.
+ */
+tt_status tt_amen_mv(const tt_mat* A, const tt_vec* x, tt_vec* y, double tol, int32_t rmax,
+                     int32_t max_sweeps, tt_step_info* info, tt_stream stream);
+
+/*
  * tt_power_step_batched - one power step of each of `count` independent
  * solvers (for example a parameter study of many small problems; each
  * instance is the iteration of eq. TT_k_eff_fixed_points on its own data).

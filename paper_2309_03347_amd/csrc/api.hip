@@ -361,6 +361,69 @@ tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts
   });
 }
 
+tt_status tt_amen_mv(const tt_mat* A, const tt_vec* x, tt_vec* y, double tol, int32_t rmax,
+                     int32_t max_sweeps, tt_step_info* info, tt_stream stream) {
+  tt_status st = guard([&] {
+    check_mat(A, "A");
+    check_vec(x, "x");
+    TT_REQUIRE(y && y->n && y->r && y->rcap && y->off && y->data, "y: NULL field");
+    TT_REQUIRE(A->d == x->d && y->d == A->d, "core counts differ");
+    for (int k = 0; k < A->d; ++k) {
+      TT_REQUIRE(A->m[k] == A->n[k], "A must be square in every mode");
+      TT_REQUIRE(A->n[k] == x->n[k] && y->n[k] == A->m[k], "modes differ");
+    }
+    TT_REQUIRE(tol > 0.0 && rmax >= 1 && max_sweeps >= 1, "bad tolerance, rank cap or sweeps");
+    const int d = A->d;
+    hipStream_t hs = (hipStream_t)stream;
+    // identity operator (the "H" of the projected product) and a zero F part
+    std::vector<int> ones(d + 1, 1);
+    std::vector<int64_t> ioff(d, 0);
+    std::vector<double> hid;
+    for (int k = 0; k < d; ++k) {
+      ioff[k] = (int64_t)hid.size();
+      for (int i = 0; i < A->n[k]; ++i)
+        for (int j = 0; j < A->n[k]; ++j) hid.push_back(i == j ? 1.0 : 0.0);
+    }
+    const size_t f0n = (size_t)A->R[0] * A->m[0] * A->n[0] * A->R[1];
+    double* tmp = nullptr;
+    TT_HIP(hipMalloc(&tmp, (hid.size() + f0n) * sizeof(double)));
+    struct Free {
+      double* p;
+      ~Free() { if (p) (void)hipFree(p); }
+    } guard_tmp{tmp};
+    TT_HIP(hipMemcpy(tmp, hid.data(), hid.size() * sizeof(double), hipMemcpyHostToDevice));
+    TT_HIP(hipMemset(tmp + hid.size(), 0, f0n * sizeof(double)));
+    tt_problem prob{};
+    prob.H = tt_mat{d, A->n, A->n, ones.data(), tmp, ioff.data()};
+    prob.SF = *A;
+    prob.F_core0 = tmp + hid.size();
+    prob.cF = *x;
+    prob.psi0 = *x;
+    prob.k0 = 1.0;
+    tt_solver_opts o{};
+    o.tol = tol;
+    o.rmax = rmax;
+    o.kick = 4;
+    o.max_sweeps = max_sweeps;
+    o.rhs_mode = 0;
+    o.gmres_restart = 40;
+    o.gmres_max_iter = 200;
+    o.direct_max = 256;
+    Solver sv;
+    sv.product_only = true;
+    sv.create(&prob, &o);
+    const TTv& p = sv.psi;
+    sv.step(hs, info);
+    for (int k = 0; k <= d; ++k)
+      if (y->rcap[k] < p.r[k]) throw CapacityError{"y capacity below the ranks of the product"};
+    for (int k = 0; k < d; ++k) copy(hs, p.core(k), y->data + y->off[k], p.size(k));
+    for (int k = 0; k <= d; ++k) y->r[k] = p.r[k];
+    TT_HIP(hipStreamSynchronize(hs));
+  });
+  if (st == TT_OK && info && info->status == TT_E_NOCONV) return TT_E_NOCONV;
+  return st;
+}
+
 tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream) {
   tt_status st = guard([&] {
     TT_REQUIRE(s != nullptr, "NULL solver");

@@ -28,6 +28,9 @@ struct Solver {
   double cap_eta = 1e-2;       // local residual reduction while the rank cap binds
   int min_sweeps = 2;          // sweeps before the stagnation test may stop
   bool cap_bound = false;      // the rank cap bound during the previous sweep
+  // Product mode: the solver computes x <- round(A x) by the same alternating
+  // sweeps with H the identity (no eigenvalue update, no normalization).
+  bool product_only = false;
   std::vector<char> Hdiag;
   // structure of each core in its mode, used by the contractions: H's
   // mode-diagonal cores (kind 1), S + F/k's cores with proportional columns

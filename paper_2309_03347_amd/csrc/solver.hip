@@ -529,7 +529,7 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
     w.cap = rw_cap;
     orth_right(s, psi, w);
     sumsq(s, psi.core(0), psi.size(0), scal + NRM2);
-    scale_inv_sqrt(s, psi.core(0), psi.size(0), scal + NRM2);
+    if (!product_only) scale_inv_sqrt(s, psi.core(0), psi.size(0), scal + NRM2);
     w.used = 0;
     dot_tt(s, cF, psi, scal + DEN, w);
   }
@@ -744,6 +744,26 @@ Co Solver::step_co(hipStream_t s, tt_step_info* info) {
   w.used = 0;
   // the left-to-right sweep left cores 0..d-2 orthonormal (QR of each split)
   co_await round_tt_co(s, X, tol, rmax, &trunc, w, slot, hb, true);
+  if (product_only) {
+    // the rounded product replaces psi as it is (no k update, no scaling)
+    psi.r = X.r;
+    for (int k = 0; k < d; ++k) copy(s, X.core(k), psi.core(k), X.size(k));
+    co_await Sync{&slot, s};
+    if (probe.active) probe.close();
+    if (info) {
+      *info = tt_step_info{};
+      info->max_local_res = max_res;
+      info->trunc_err = trunc;
+      info->sweeps = sweeps;
+      int mr = 0;
+      for (int v : psi.r) mr = std::max(mr, v);
+      info->max_rank = mr;
+      info->local_iters = st.local_iters;
+      info->status = max_res < tol ? TT_OK : TT_E_NOCONV;
+    }
+    last_launches = g_launches;
+    co_return;
+  }
   w.used = 0;
   dot_tt(s, cF, X, scal + NUM, w);
   k_update(s, scal + KVAL, scal + NUM, scal + DEN, scal + KINFO);

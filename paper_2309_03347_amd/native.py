@@ -26,7 +26,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
-            "tt_local_apply", "ttnt_release"]
+            "tt_local_apply", "ttnt_release", "tt_amen_mv"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -137,6 +137,9 @@ def lib():
         L.ttnt_set_grid_wait_limit.argtypes = [ctypes.c_double]
         L.tt_orth_right.argtypes = [ctypes.POINTER(TTVec), v, ctypes.c_size_t, v]
         L.ttnt_release.argtypes = []
+        L.tt_amen_mv.argtypes = [ctypes.POINTER(TTMat), ctypes.POINTER(TTVec), ctypes.POINTER(TTVec),
+                                 ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(TTStepInfo), v]
         L.tt_local_apply_workspace.argtypes = [ctypes.POINTER(TTLocal)]
         L.tt_local_apply_workspace.restype = ctypes.c_size_t
         L.tt_local_apply.argtypes = [ctypes.POINTER(TTLocal), v, v, ctypes.c_int32, v,
@@ -364,6 +367,18 @@ def tt_local_solve_noalloc(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1
     torch.cuda.synchronize()
     return x, dict(iterations=info.iterations, method=info.method_used, rel_res=info.rel_res,
                    converged=st == TT_OK)
+
+
+def tt_amen_mv(A: "DeviceTTMat", x: DeviceTT, y: DeviceTT, tol: float, rmax: int,
+               max_sweeps: int = 20) -> dict:
+    """y ~ A x by alternating sweeps (ranks chosen by tol, capped at rmax)."""
+    info = TTStepInfo()
+    yd = y.desc()
+    st = lib().tt_amen_mv(ctypes.byref(A.desc()), ctypes.byref(x.desc()), ctypes.byref(yd),
+                          float(tol), int(rmax), int(max_sweeps), ctypes.byref(info), _stream())
+    _check(st, allow=(TT_E_NOCONV,))
+    return dict(sweeps=info.sweeps, max_local_res=info.max_local_res, trunc_err=info.trunc_err,
+                max_rank=info.max_rank, converged=st == TT_OK)
 
 
 def release() -> None:
