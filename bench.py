@@ -34,12 +34,15 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 
 # HBM bytes per launch of a kernel class from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# counters scaled by a plain copy (profiles/gmres_slices_inner_box_n32_G4_S4_traffic.md),
+# counters scaled by a plain copy (profiles/gmres_slices_checkerboard_n128_G8_S8_traffic.md),
 # valid only while the kernel's sources are unchanged.
 MEASURED_TRAFFIC = {
-    ("krylov", "inner_box_n32_G4_S4"): dict(
-        bytes_per_launch=19.35e6,
-        sources={"paper_2309_03347_amd/csrc/krylov.hip": "d41a4ce71ddb971a",
+    # HBM bytes per launch of the dominant kernel from FETCH_SIZE (scaled by
+    # 2.0) plus WRITE_SIZE (scaled by 1.0) over the timed steps of a profiled
+    # bench run, valid while the kernel sources hash to the prefixes below
+    ("krylov", "checkerboard_n128_G8_S8"): dict(
+        bytes_per_launch=175.1e6,
+        sources={"paper_2309_03347_amd/csrc/krylov.hip": "7e598c95c04d2eac",
                  "paper_2309_03347_amd/csrc/gemm_tile.h": "8641b1e5a94501dd"}),
 }
 
