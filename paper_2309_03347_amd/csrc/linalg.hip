@@ -337,6 +337,206 @@ __global__ __launch_bounds__(WG) void lu_solve_kernel(double* __restrict__ Ag, i
     for (int e = tid; e < N; e += nt) bg[e] = b[e];
 }
 
+// Blocked right-looking LU with partial pivoting and solve, for systems whose
+// matrix stays in global memory.  Per panel of kLuNB columns: the panel
+// (rows k0..N-1) is factored in LDS, its row interchanges are applied to the
+// columns on its right and to b, the block row of U is formed by forward
+// substitution with the panel's unit lower triangle, and the trailing matrix
+// takes one rank-kLuNB update, so it is read and written once per panel
+// instead of once per column.  b is eliminated along, and the back
+// substitution runs by blocks of kLuNB rows (row-wise, coalesced dot
+// products, then the block's triangle).  The pivot rule (largest magnitude,
+// lowest row on ties) and the zero-pivot convention are those of
+// lu_solve_kernel.
+constexpr int kLuNB = 16, kLuP = kLuNB + 1, kLuUC = 64;
+
+size_t lu_blocked_lds_doubles(int N) {
+  return (size_t)N * kLuP + (size_t)kLuNB * kLuUC + (size_t)N + 8;
+}
+
+__global__ __launch_bounds__(WG) void lu_blocked_kernel(double* __restrict__ Ag, int N, int lda,
+                                                        double* __restrict__ bg) {
+  extern __shared__ double sm[];
+  double* A = Ag + (int64_t)blockIdx.x * N * lda;
+  double* bo = bg + (int64_t)blockIdx.x * N;
+  double* Pr = sm;                            // panel: rows k0..N-1, kLuNB columns, pitch kLuP
+  double* Us = Pr + (size_t)N * kLuP;         // kLuNB x kLuUC chunk of the U block row
+  double* xs = Us + kLuNB * kLuUC;            // b, eliminated along; then x
+  __shared__ double sval[WG / 64];
+  __shared__ int sidx[WG / 64];
+  __shared__ int piv[kLuNB];
+  constexpr int NW = WG / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int e = tid; e < N; e += WG) xs[e] = bo[e];
+  for (int k0 = 0; k0 < N; k0 += kLuNB) {
+    const int nb = min(kLuNB, N - k0), R = N - k0, C0 = k0 + nb;
+    __syncthreads();
+    for (int e = tid; e < R * nb; e += WG) {
+      const int r = e / nb, c = e - r * nb;
+      Pr[r * kLuP + c] = A[(int64_t)(k0 + r) * lda + k0 + c];
+    }
+    __syncthreads();
+    // factor the panel (rows relative to k0)
+    for (int j = 0; j < nb; ++j) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < R; i += WG) {
+        const double x = fabs(Pr[i * kLuP + j]);
+        if (x > best) { best = x; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) { sval[wid] = best; sidx[wid] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double bb = -1.0;
+        int ii = j;
+        for (int w = 0; w < NW; ++w)
+          if (sval[w] > bb || (sval[w] == bb && sidx[w] < ii)) { bb = sval[w]; ii = sidx[w]; }
+        piv[j] = ii;
+      }
+      __syncthreads();
+      const int p = piv[j];
+      if (p != j && tid < nb) {
+        const double t = Pr[j * kLuP + tid];
+        Pr[j * kLuP + tid] = Pr[p * kLuP + tid];
+        Pr[p * kLuP + tid] = t;
+      }
+      __syncthreads();
+      const double d = Pr[j * kLuP + j];
+      const double id = d != 0.0 ? 1.0 / d : 0.0;
+      for (int i = j + 1 + tid; i < R; i += WG) {
+        const double l = Pr[i * kLuP + j] * id;
+        Pr[i * kLuP + j] = l;
+        for (int c = j + 1; c < nb; ++c) Pr[i * kLuP + c] -= l * Pr[j * kLuP + c];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < R * nb; e += WG) {
+      const int r = e / nb, c = e - r * nb;
+      A[(int64_t)(k0 + r) * lda + k0 + c] = Pr[r * kLuP + c];
+    }
+    // interchanges on the columns right of the panel (each thread its own
+    // columns, in pivot order), then the block row of U by forward
+    // substitution with the unit lower triangle of the panel
+    for (int c = C0 + tid; c < N; c += WG) {
+      double u[kLuNB];
+#pragma unroll
+      for (int t = 0; t < kLuNB; ++t) u[t] = 0.0;
+      for (int j = 0; j < nb; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+          const double t = A[(int64_t)(k0 + j) * lda + c];
+          A[(int64_t)(k0 + j) * lda + c] = A[(int64_t)(k0 + p) * lda + c];
+          A[(int64_t)(k0 + p) * lda + c] = t;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kLuNB; ++t)
+        if (t < nb) u[t] = A[(int64_t)(k0 + t) * lda + c];
+#pragma unroll
+      for (int t = 1; t < kLuNB; ++t)
+#pragma unroll
+        for (int q = 0; q < t; ++q)
+          if (t < nb) u[t] -= Pr[t * kLuP + q] * u[q];
+#pragma unroll
+      for (int t = 1; t < kLuNB; ++t)
+        if (t < nb) A[(int64_t)(k0 + t) * lda + c] = u[t];
+    }
+    if (tid == 0) {
+      for (int j = 0; j < nb; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+          const double t = xs[k0 + j];
+          xs[k0 + j] = xs[k0 + p];
+          xs[k0 + p] = t;
+        }
+      }
+      for (int t = 1; t < nb; ++t) {
+        double v = xs[k0 + t];
+        for (int q = 0; q < t; ++q) v -= Pr[t * kLuP + q] * xs[k0 + q];
+        xs[k0 + t] = v;
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12 by chunks of kLuUC columns: lane = column,
+    // wavefront = every NW-th row, four rows in flight per wavefront
+    for (int cc = C0; cc < N; cc += kLuUC) {
+      const int cw = min(kLuUC, N - cc);
+      for (int e = tid; e < kLuNB * kLuUC; e += WG) {
+        const int t = e / kLuUC, cl = e - t * kLuUC;
+        Us[e] = (t < nb && cl < cw) ? A[(int64_t)(k0 + t) * lda + cc + cl] : 0.0;
+      }
+      __syncthreads();
+      if (lane < cw) {
+        double uv[kLuNB];
+#pragma unroll
+        for (int t = 0; t < kLuNB; ++t) uv[t] = Us[t * kLuUC + lane];
+        double* col = A + cc + lane;
+        int r = nb + wid;
+        for (; r + 3 * NW < R; r += 4 * NW) {
+          double v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = col[(int64_t)(k0 + r + q * NW) * lda];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double* lr = Pr + (r + q * NW) * kLuP;
+#pragma unroll
+            for (int t = 0; t < kLuNB; ++t) v[q] -= lr[t] * uv[t];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) col[(int64_t)(k0 + r + q * NW) * lda] = v[q];
+        }
+        for (; r < R; r += NW) {
+          const double* lr = Pr + r * kLuP;
+          double v = col[(int64_t)(k0 + r) * lda];
+#pragma unroll
+          for (int t = 0; t < kLuNB; ++t) v -= lr[t] * uv[t];
+          col[(int64_t)(k0 + r) * lda] = v;
+        }
+      }
+      __syncthreads();
+    }
+    // the same update of b (uv of columns beyond nb are zero above; here the
+    // panel's unused columns are never read)
+    for (int r = nb + tid; r < R; r += WG) {
+      const double* lr = Pr + r * kLuP;
+      double v = xs[k0 + r];
+      for (int t = 0; t < nb; ++t) v -= lr[t] * xs[k0 + t];
+      xs[k0 + r] = v;
+    }
+  }
+  __syncthreads();
+  // back substitution by blocks of kLuNB rows, from the bottom
+  for (int i0 = ((N - 1) / kLuNB) * kLuNB; i0 >= 0; i0 -= kLuNB) {
+    const int nb = min(kLuNB, N - i0), c1 = i0 + nb;
+    for (int ii = wid; ii < nb; ii += NW) {
+      const int i = i0 + ii;
+      const double* row = A + (int64_t)i * lda;
+      double acc = 0.0;
+      for (int c = c1 + lane; c < N; c += 64) acc = fma(row[c], xs[c], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) xs[i] -= acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int ii = nb - 1; ii >= 0; --ii) {
+        const int i = i0 + ii;
+        const double* row = A + (int64_t)i * lda;
+        double v = xs[i];
+        for (int c = i + 1; c < c1; ++c) v -= row[c] * xs[c];
+        const double d = row[i];
+        xs[i] = d != 0.0 ? v / d : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < N; e += WG) bo[e] = xs[e];
+}
+
 // ---------------------------------------------------------------------------
 // LDS-resident factorizations, one workgroup of 256 threads (4 wavefronts).
 // Matrices are held column-major with an odd leading dimension so that lanes
@@ -1001,6 +1201,8 @@ int lds_limit() {
       TT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_solve_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_blocked_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(
         reinterpret_cast<const void*>(gj_solve_kernel<kGjExtR, kGjExtC, kGjExtTC, kGjExtCE>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::min<size_t>(kGjExtLds, v)));
@@ -1081,7 +1283,8 @@ void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   ++g_launches;
   // One workgroup per system.  Gauss-Jordan up to 240 unknowns, with the
   // augmented matrix in registers (up to 192) or in registers and LDS; larger
-  // systems use the LU kernel (in global memory beyond 141 unknowns).
+  // systems use the LU kernel (in LDS up to 141 unknowns), blocked by panels
+  // beyond that while a panel fits LDS (about 1,000 unknowns).
   if (N <= 64) {
     gj_solve_kernel<4, 3, 32><<<batch, 512, 0, s>>>(A, N, lda, b);
   } else if (N <= 112) {
@@ -1096,7 +1299,11 @@ void lu_solve(hipStream_t s, double* A, int N, int lda, double* b, int batch) {
   } else {
     const size_t need = ((size_t)N * odd_ld(N) + N) * 8;
     const bool lds = need <= (size_t)lds_limit();
-    lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);
+    const size_t need_blk = lu_blocked_lds_doubles(N) * 8;
+    if (!lds && need_blk <= (size_t)lds_limit())
+      lu_blocked_kernel<<<batch, WG, need_blk, s>>>(A, N, lda, b);
+    else
+      lu_solve_kernel<<<batch, WG, lds ? need : 0, s>>>(A, N, lda, b, lds ? 1 : 0);
   }
   TT_HIP(hipGetLastError());
 }

@@ -172,14 +172,17 @@ def _local_system(rng, ra, RL, n, RR, rc, shift=8.0):
     (1, 7, 3, 2, 3, 14),     # N = 196: two column blocks in LDS
     (1, 9, 3, 2, 3, 13),     # N = 234, a system of the 32^3 case
     (1, 8, 3, 2, 3, 15),     # N = 240: largest Gauss-Jordan solve
-    (1, 5, 3, 2, 4, 25),     # N = 250: LU in global memory
+    (1, 5, 3, 2, 4, 25),     # N = 250: blocked LU (panels in LDS)
+    (1, 7, 3, 2, 3, 37),     # N = 518: blocked LU, ragged last panel
+    (1, 10, 2, 2, 2, 55),    # N = 1100: panel outside LDS, unblocked LU in global memory
     (2, 6, 4, 2, 5, 7),      # GMRES
     (2, 16, 6, 2, 6, 16),
     (0, 4, 3, 24, 3, 5),     # automatic (angle-like core): 24 blocks of 20
     (3, 4, 3, 3, 3, 36),     # blocks of 144, as at the angle core of the 32^3 case
     (3, 6, 3, 3, 3, 32),     # blocks of 192
-    (3, 5, 3, 3, 3, 40),     # blocks of 200: LU in global memory
-    (3, 8, 3, 6, 3, 68),     # blocks of 544 (rank 8 | rank 64 + kick): LU outside LDS
+    (3, 5, 3, 3, 3, 40),     # blocks of 200: blocked LU
+    (3, 8, 3, 6, 3, 68),     # blocks of 544 (rank 8 | rank 64 + kick): blocked LU
+    (3, 8, 2, 3, 2, 132),    # blocks of 1056: the largest blocked-LU panel
 ])
 def test_local_solve_matches_dense(cuda, method, ra, RL, n, RR, rc):
     from paper_2309_03347_amd import native
