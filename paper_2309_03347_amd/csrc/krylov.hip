@@ -55,10 +55,17 @@ struct SArgs {
   void* W;              // N, working precision: current direction, published each step
   double* Q;            // r0 x (n RR) x (r0 n): folded operator per slice (FP64)
   void* Qw;             // the same in the working precision (Q itself in FP64 mode)
+  double* Qf;           // general matrix-core form: Q_a in fragment order, qf_slice per slice
+  void* Qfw;            // the same in the working precision (Qf itself in FP64 mode)
+  int64_t qf_slice;
+  int S;                // general matrix-core form: workgroups per slice (1 otherwise)
+  double* Py;           // with S > 1: per workgroup partial products (n r1 each)
   double* Pd1;          // G x (m + 1)
   double* Pd2;          // G x (m + 1)
   double* Pn;           // G x 2
   int m, max_iter, spw, ldv;
+  int ts_doubles;       // LDS room of the first product's T (doubles)
+  int mfg_bt;           // general matrix-core form: beta' tiles of 16 per chunk
   double tol, eta;
   double inner_tol;     // mixed mode: an inner cycle stops at this fraction of its start residual
   unsigned* bar;        // grid barrier: count, epoch flag (+32), abort word (+48)
@@ -373,6 +380,7 @@ __device__ __forceinline__ void load_qfrag(const E* __restrict__ Qa, int M1, int
 struct Ctx {
   int G, b, tid, lane;
   int m, ldv, nr1, nr0, nRR, a0, a1, nloc, K3;
+  int sub, own0;  // with S > 1: the workgroup's index within its slice, first own element
   int64_t e0;
   int TNf, Kp, Np;
   double* As;     // GEMM staging (kAsDoubles doubles of room)
@@ -423,16 +431,19 @@ __device__ __forceinline__ void stage3(const SArgs& a, const Ctx& c, const E* ph
   __syncthreads();
 }
 
-// The matrix-core kernel's form: every thread streams part of one row
-// of PhiR, P = 256 / r1 lanes per row (any P), and the P partial sums of a
-// row are added in a fixed order through LDS (red: 4 x 256 doubles).
-template <typename E>
-__device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const E* phiRe,
-                                            const E* Ts, E* ys) {
+// The matrix-core kernels' form: every thread streams part of one row of
+// PhiR, P = 256 / r1 lanes per row (any P), and the P partial sums of a row
+// are added in a fixed order through LDS (red: 4 x 256 doubles).  T rows have
+// length K (row i at Ts + i K) and meet the first K elements of each PhiR row
+// starting at phiRe (row stride K3); with accum the sums are added to ys.
+template <typename E, bool Pipe = true>
+__device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const E* phiRe, int K,
+                                            const E* Ts, E* ys, bool accum) {
   constexpr int W = 16 / (int)sizeof(E);
-  const int tid = c.tid, K = c.K3;
+  const int tid = c.tid;
   const int P = max(1, min(64, kThreads / a.r1)), rows = kThreads / P;
-  const bool w2 = (K % W == 0) && ((reinterpret_cast<uintptr_t>(phiRe) & 15) == 0);
+  const bool w2 = (K % W == 0) && (c.K3 % W == 0) &&
+                  ((reinterpret_cast<uintptr_t>(phiRe) & 15) == 0);
   E* red = reinterpret_cast<E*>(c.As);
   for (int c0 = 0; c0 < a.r1; c0 += rows) {
     const int cr = c0 + tid / P, part = tid % P;
@@ -440,11 +451,11 @@ __device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const 
       const int ni = min(2, a.n - i0);
       E acc[2] = {E(0), E(0)};
       if (tid < rows * P && cr < a.r1) {
-        const E* pr = phiRe + (int64_t)cr * K;
+        const E* pr = phiRe + (int64_t)cr * c.K3;
         const E* t2 = Ts + (int64_t)i0 * K;
         // ranks 33-36 and 29-32 (P = 7, 8) take the pipelined stream
-        if (w2 && ni == 2 && P == 7) row_dots_pipe<2, W, 7, E>(pr, t2, K, part, P, acc);
-        else if (w2 && ni == 2 && P == 8) row_dots_pipe<2, W, 8, E>(pr, t2, K, part, P, acc);
+        if (Pipe && w2 && ni == 2 && P == 7) row_dots_pipe<2, W, 7, E>(pr, t2, K, part, P, acc);
+        else if (Pipe && w2 && ni == 2 && P == 8) row_dots_pipe<2, W, 8, E>(pr, t2, K, part, P, acc);
         else if (ni == 2) row_dots<2, E>(pr, t2, K, part, P, acc);
         else row_dots<1, E>(pr, t2, K, part, P, acc);
       }
@@ -455,7 +466,8 @@ __device__ __forceinline__ void stage3_pipe(const SArgs& a, const Ctx& c, const 
         for (int q = 0; q < ni; ++q) {
           E sum = E(0);
           for (int p = 0; p < P; ++p) sum += red[q * kThreads + tid * P + p];
-          ys[(i0 + q) * a.r1 + c0 + tid] = sum;
+          E* o = ys + (i0 + q) * a.r1 + c0 + tid;
+          *o = accum ? *o + sum : sum;
         }
       }
       __syncthreads();
@@ -586,14 +598,286 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const E* Qe, cons
     }
   }
   __syncthreads();
-  stage3_pipe<E>(a, c, phiRe, Ts, out);
+  stage3_pipe<E>(a, c, phiRe, c.K3, Ts, out, false);
+}
+
+// The general matrix-core form's second product: y[i][c] (+)= sum_{k < K}
+// T[i][k] PhiR[c][k] with T rows of length K in LDS (row i at Ts + i K) and
+// PhiR rows starting at phiRe (row stride K3).  A wavefront takes four rows c
+// at a time with its lanes along k (16-byte loads of two consecutive
+// elements when the rows are aligned), so every load of PhiR uses whole cache
+// lines and each T value read from LDS serves four rows; the 64 lanes' sums are
+// added by a butterfly.
+template <typename E, typename O>
+__device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K, const E* Ts,
+                            O* ys, bool accum) {
+  constexpr int CR = 4;
+  typedef E V2 __attribute__((ext_vector_type(2)));
+  const int w = c.tid >> 6, l = c.lane, n = a.n, r1 = a.r1;
+  const int64_t K3 = c.K3;
+  const bool vec = (K % 2 == 0) && (K3 % 2 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(phiRe) & (2 * sizeof(E) - 1)) == 0);
+  for (int c0 = CR * w; c0 < r1; c0 += 4 * CR) {
+    const int nr = min(CR, r1 - c0);
+    for (int i0 = 0; i0 < n; i0 += 2) {
+      const bool two = i0 + 1 < n;
+      double acc[CR][2];
+#pragma unroll
+      for (int r = 0; r < CR; ++r) acc[r][0] = acc[r][1] = 0.0;
+      const E* t0 = Ts + (int64_t)i0 * K;
+      const E* t1 = two ? t0 + K : t0;
+      if (vec) {
+        const int K2 = K / 2;
+        const V2* ta = reinterpret_cast<const V2*>(t0);
+        const V2* tb = reinterpret_cast<const V2*>(t1);
+        const V2* prow[CR];
+#pragma unroll
+        for (int r = 0; r < CR; ++r)
+          prow[r] = reinterpret_cast<const V2*>(phiRe + (int64_t)(c0 + min(r, nr - 1)) * K3);
+        constexpr int U = 4;   // k positions per lane in flight: U CR 16-byte loads
+        int k = l;
+        for (; k + 64 * (U - 1) < K2; k += 64 * U) {
+          V2 pv[U][CR], x0[U], x1[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < CR; ++r) pv[u][r] = prow[r][k + 64 * u];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            x0[u] = ta[k + 64 * u];
+            x1[u] = tb[k + 64 * u];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < CR; ++r) {
+              acc[r][0] = fma((double)x0[u].x, (double)pv[u][r].x, acc[r][0]);
+              acc[r][0] = fma((double)x0[u].y, (double)pv[u][r].y, acc[r][0]);
+              acc[r][1] = fma((double)x1[u].x, (double)pv[u][r].x, acc[r][1]);
+              acc[r][1] = fma((double)x1[u].y, (double)pv[u][r].y, acc[r][1]);
+            }
+        }
+        for (; k < K2; k += 64) {
+          const V2 x0 = ta[k], x1 = tb[k];
+#pragma unroll
+          for (int r = 0; r < CR; ++r) {
+            const V2 pv = prow[r][k];
+            acc[r][0] = fma((double)x0.x, (double)pv.x, acc[r][0]);
+            acc[r][0] = fma((double)x0.y, (double)pv.y, acc[r][0]);
+            acc[r][1] = fma((double)x1.x, (double)pv.x, acc[r][1]);
+            acc[r][1] = fma((double)x1.y, (double)pv.y, acc[r][1]);
+          }
+        }
+      } else {
+        for (int k = l; k < K; k += 64) {
+          const E x0 = t0[k], x1 = t1[k];
+#pragma unroll
+          for (int r = 0; r < CR; ++r) {
+            const E p = r < nr ? phiRe[(int64_t)(c0 + r) * K3 + k] : E(0);
+            acc[r][0] = fma((double)x0, (double)p, acc[r][0]);
+            acc[r][1] = fma((double)x1, (double)p, acc[r][1]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < CR; ++r) {
+        acc[r][0] = wave_sum(acc[r][0]);
+        acc[r][1] = wave_sum(acc[r][1]);
+      }
+      if (l == 0) {
+        for (int r = 0; r < nr; ++r)
+          for (int q = 0; q < (two ? 2 : 1); ++q) {
+            O* o = ys + (int64_t)(i0 + q) * r1 + c0 + r;
+            const O v = (O)acc[r][q];
+            *o = accum ? *o + v : v;
+          }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// General matrix-core form for one slice per workgroup, any n RR and n r0
+// (n <= 4, r1 <= 96).  The rows (i, beta') of Q_a are taken in chunks that
+// hold the same range of 16 bt beta' for every i (at most 64 rows), so each
+// chunk's part of the second product reads one range of every PhiR row.  The
+// first product of a chunk runs over k in steps of KC: the chunk's rows of
+// Q_a (into As, from a copy laid out in fragment order once per solve, see
+// qf_reorder) and KC rows of v (into Bs) are staged in fragment order, the
+// next step's values loaded into registers while the current one is
+// multiplied; wavefront w owns the (m-tile, n-tile) pairs w, w + 4, ... and
+// keeps their accumulators over the k steps.  The chunk's T goes to Ts and
+// its part of the second product is added to out.  With S workgroups per
+// slice each takes every S-th chunk and writes its partial product; the sum
+// of the S partials is formed after a grid barrier (mfg_reduce).
+constexpr int kMfgPairs = 6;     // (m-tile, n-tile) pairs per wavefront: 4 m-tiles x 6 n-tiles
+constexpr int kMfgRows = 64;     // rows of Q_a per chunk
+
+__host__ __device__ inline int mfg_bt(int n, int RR) {
+  const int bt = kMfgRows / (16 * n);
+  const int need = (RR + 15) / 16;
+  return bt < need ? bt : need;
+}
+__host__ __device__ inline int mfg_kc(int n, int bt, int r1) {
+  // k-steps of 4 per stage: the chunk's A fragments and v's fragments each fit
+  // 2048 elements (eight per thread)
+  const int nt = (r1 + 15) / 16;
+  int ks = 32 / (n * bt);
+  if (32 / nt < ks) ks = 32 / nt;
+  if (ks > 16) ks = 16;
+  return 4 * ks;
+}
+
+// Q_a (row-major, n RR x K1) into the general matrix-core form's order: for
+// each chunk of beta' (16 BT at a time) and each k step of KC, the chunk's
+// fragments (m-tile, k-step) of 64 lanes, lane l holding A[l % 16][l / 16] of
+// its fragment, zero past the rows and columns.  Once per solve, by the
+// workgroup that owns the slice (with S > 1, each of the slice's workgroups
+// for its own chunks).
+template <typename E>
+__device__ void qf_reorder(const SArgs& a, int sub, const double* Qa, E* Qs) {
+  const int K1 = a.n * a.r0, RR = a.RR, n = a.n, BT = a.mfg_bt;
+  const int KC = mfg_kc(n, BT, a.r1), KS = KC / 4, nkc = cdiv(K1, KC);
+  const int64_t full = (int64_t)n * BT * KS * 64 * nkc;
+  for (int64_t f = threadIdx.x; f < a.qf_slice; f += kThreads) {
+    const int ci = (int)(f / full);
+    if (ci % a.S != sub) continue;      // another workgroup's chunk
+    const int64_t rem = f - ci * full;
+    const int b0 = 16 * BT * ci, bc = min(16 * BT, RR - b0), tpi = cdiv(bc, 16);
+    const int per = n * tpi * KS * 64;
+    const int j = (int)(rem / per), e = (int)(rem - (int64_t)j * per);
+    const int frag = e >> 6, ln = e & 63, mt = frag / KS, ks = frag - mt * KS;
+    const int i = mt / tpi, bp = 16 * (mt - i * tpi) + (ln & 15);
+    const int kk = j * KC + 4 * ks + (ln >> 4);
+    Qs[f] = (bp < bc && kk < K1) ? (E)Qa[(int64_t)(i * RR + b0 + bp) * K1 + kk] : E(0);
+  }
+  __syncthreads();
+}
+
+template <typename E, typename O>
+__device__ void apply_slice_mfg(const SArgs& a, const Ctx& c, const E* Qfe, const E* phiRe,
+                                const E* v, E alpha, O* out) {
+  typedef MfmaOps<E> Ops;
+  typedef typename Ops::Acc Acc;
+  const int tid = c.tid, l = c.lane, w = tid >> 6;
+  const int K1 = c.nr0, RR = a.RR, n = a.n, r1 = a.r1;
+  const int NT = cdiv(r1, 16);
+  const int BT = a.mfg_bt, KC = mfg_kc(n, BT, r1), KS = KC / 4;
+  E* As = reinterpret_cast<E*>(c.As);
+  E* Bs = reinterpret_cast<E*>(c.Bs);
+  E* Ts = reinterpret_cast<E*>(c.Ts);
+  const int nkc = cdiv(K1, KC);
+  const E* Qs = Qfe + (int64_t)c.a0 * a.qf_slice;
+  // staging: A chunk (MT m-tiles x KS k-steps fragments) and B (KS x NT fragments),
+  // at most 8 + 8 elements per thread and step
+  constexpr int kSA = 8, kSB = 8;
+  // with S > 1 the workgroup takes chunks sub, sub + S, ... and out is its
+  // partial product (zero when it has no chunk)
+  if (16 * BT * c.sub >= RR) {
+    for (int e = tid; e < n * r1; e += kThreads) out[e] = O(0);
+    __syncthreads();
+  }
+  for (int b0 = 16 * BT * c.sub; b0 < RR; b0 += 16 * BT * a.S) {
+    const int bc = min(16 * BT, RR - b0);      // beta' rows of the chunk, for every i
+    const int tpi = cdiv(bc, 16);
+    const int MT = n * tpi;                    // m-tiles of the chunk
+    const int npairs = MT * NT;
+    const int na = MT * KS * 64, nbv = KS * NT * 64;
+    E ra[kSA], rb[kSB];
+    // the chunk's fragments of the k step starting at K0, consecutive in Qf
+    const E* Qc = Qs + (int64_t)(b0 / 16) * n * KS * 64 * nkc;
+    auto load = [&](int K0) {
+      const E* Qk = Qc + (int64_t)(K0 / KC) * na;
+#pragma unroll
+      for (int u = 0; u < kSA; ++u) {
+        const int e = tid + u * kThreads;
+        ra[u] = e < na ? Qk[e] : E(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kSB; ++u) {
+        const int e = tid + u * kThreads;
+        E val = E(0);
+        if (e < nbv) {
+          const int frag = e >> 6, ln = e & 63, ks = frag / NT, nt = frag - ks * NT;
+          const int kk = K0 + 4 * ks + (ln >> 4), j = 16 * nt + (ln & 15);
+          if (kk < K1 && j < r1) val = ld_coh<E>(v + (int64_t)kk * r1 + j);
+        }
+        rb[u] = val;
+      }
+    };
+    Acc acc[kMfgPairs];
+#pragma unroll
+    for (int q = 0; q < kMfgPairs; ++q) acc[q] = {E(0), E(0), E(0), E(0)};
+    load(0);
+    for (int K0 = 0; K0 < K1; K0 += KC) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kSA; ++u) {
+        const int e = tid + u * kThreads;
+        if (e < na) As[e] = ra[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kSB; ++u) {
+        const int e = tid + u * kThreads;
+        if (e < nbv) Bs[e] = rb[u];
+      }
+      __syncthreads();
+      if (K0 + KC < K1) load(K0 + KC);
+#pragma unroll
+      for (int q = 0; q < kMfgPairs; ++q) {
+        const int pr = w + 4 * q;
+        if (pr < npairs) {
+          const int mt = pr / NT, nt = pr - mt * NT;
+          for (int ks = 0; ks < KS; ++ks)
+            acc[q] = Ops::mma(As[(mt * KS + ks) * 64 + l], Bs[(ks * NT + nt) * 64 + l], acc[q]);
+        }
+      }
+    }
+    // the chunk's T: Ts[(i bc + beta' - b0) r1 + d]
+#pragma unroll
+    for (int q = 0; q < kMfgPairs; ++q) {
+      const int pr = w + 4 * q;
+      if (pr < npairs) {
+        const int mt = pr / NT, nt = pr - mt * NT;
+        const int i = mt / tpi, bt = mt - i * tpi;
+        const int col = 16 * nt + (l & 15);
+        if (col < r1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int bp = 16 * bt + Ops::row(l, r);
+            if (bp < bc) Ts[(int64_t)(i * bc + bp) * r1 + col] = alpha * acc[q][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    stage3_rows<E, O>(a, c, phiRe + (int64_t)b0 * r1, bc * r1, Ts, out, b0 > 16 * BT * c.sub);
+  }
+}
+
+// out[e] = sum over the slice's S partial products of element own0 + e, for
+// the workgroup's own elements, in a fixed order (coherent loads; with S > 1
+// called after the grid barrier that follows the partial products, with S =
+// 1 it copies the workgroup's own product).
+template <typename O>
+__device__ void mfg_reduce(const SArgs& a, const Ctx& c, O* out) {
+  const double* P = a.Py + (int64_t)c.a0 * a.S * c.nr1 + c.own0;
+  for (int e = c.tid; e < c.nloc; e += kThreads) {
+    double acc = 0.0;
+    for (int q = 0; q < a.S; ++q) acc += ld_coherent(P + (int64_t)q * c.nr1 + e);
+    out[e] = (O)acc;
+  }
+  __syncthreads();
 }
 
 // The solve.  T is the working precision of the Krylov iterations; restart
 // residuals r = f - A x and x itself are always FP64.  With T = float each
 // restart cycle is one step of iterative refinement: the cycle solves
 // A d = r in FP32 to inner_tol (or to the global target) and x += d in FP64.
-template <typename T, bool MF>
+// MF selects the operator application: 0 the vector-FMA form (any slices per
+// workgroup), 1 the register-resident matrix-core form (one slice, n RR <= 128,
+// n r0 <= 80), 2 the general matrix-core form (one slice, chunked).
+template <typename T, int MF>
 __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds[];   // 16-byte reads of Ts
   __shared__ double red[4];
@@ -609,10 +893,24 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   c.nr1 = a.n * a.r1;
   c.nr0 = a.n * a.r0;
   c.nRR = a.n * a.RR;
-  c.a0 = min(a.r0, c.b * a.spw);
-  c.a1 = min(a.r0, c.a0 + a.spw);
-  c.nloc = (c.a1 - c.a0) * c.nr1;
-  c.e0 = (int64_t)c.a0 * c.nr1;
+  if (a.S > 1) {
+    // S workgroups per slice, each owning a contiguous part of the slice's
+    // n r1 elements
+    const int q = cdiv(c.nr1, a.S);
+    c.a0 = c.b / a.S;
+    c.a1 = c.a0 + 1;
+    c.sub = c.b - c.a0 * a.S;
+    c.own0 = min(c.nr1, c.sub * q);
+    c.nloc = min(c.nr1, c.own0 + q) - c.own0;
+    c.e0 = (int64_t)c.a0 * c.nr1 + c.own0;
+  } else {
+    c.a0 = min(a.r0, c.b * a.spw);
+    c.a1 = min(a.r0, c.a0 + a.spw);
+    c.sub = 0;
+    c.own0 = 0;
+    c.nloc = (c.a1 - c.a0) * c.nr1;
+    c.e0 = (int64_t)c.a0 * c.nr1;
+  }
   c.K3 = a.RR * a.r1;
   c.TNf = a.r1 <= 32 ? 32 : 64;
   c.Kp = cdiv(c.nr0, 16) * 16;
@@ -620,7 +918,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   c.As = lds;
   c.Bs = c.As + kAsDoubles;
   c.Ts = c.Bs + kBsDoubles;
-  c.Yd = c.Ts + (int64_t)c.nRR * a.r1;
+  c.Yd = c.Ts + a.ts_doubles;
   c.Hpk = c.Yd + c.ldv;
   c.hcol = c.Hpk + c.m * (c.m + 1) / 2;
   c.h2 = c.hcol + (c.m + 2);
@@ -648,14 +946,35 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   // Q_a for the own slices (once per solve; read back by this workgroup only)
   for (int s = c.a0; s < c.a1; ++s) {
     double* Qa = a.Q + (int64_t)s * c.nRR * c.nr0;
-    for (int j = 0; j < a.n; ++j)
-      wg_gemm<false>(c.nRR, a.r0, a.RL, 1.0, Strided{a.Ap + j, (int64_t)a.RL * a.n, a.n},
-                     Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1}, Qa + j, c.nr0, a.n,
-                     c.As, c.Bs);
-    if (kMixed) {
+    if (MF == 2 && a.S > 1) {
+      // only the rows (i, beta') of the workgroup's own chunks
+      const int bstep = 16 * a.mfg_bt;
+      for (int b0 = bstep * c.sub; b0 < a.RR; b0 += bstep * a.S) {
+        const int bc = min(bstep, a.RR - b0);
+        for (int i = 0; i < a.n; ++i) {
+          const int64_t row0 = (int64_t)i * a.RR + b0;
+          for (int j = 0; j < a.n; ++j)
+            wg_gemm<false>(bc, a.r0, a.RL, 1.0,
+                           Strided{a.Ap + row0 * a.RL * a.n + j, (int64_t)a.RL * a.n, a.n},
+                           Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1},
+                           Qa + row0 * c.nr0 + j, c.nr0, a.n, c.As, c.Bs);
+        }
+      }
+    } else {
+      for (int j = 0; j < a.n; ++j)
+        wg_gemm<false>(c.nRR, a.r0, a.RL, 1.0, Strided{a.Ap + j, (int64_t)a.RL * a.n, a.n},
+                       Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1}, Qa + j, c.nr0,
+                       a.n, c.As, c.Bs);
+    }
+    if (kMixed && MF != 2) {
       T* Qt = reinterpret_cast<T*>(a.Qw) + (int64_t)s * c.nRR * c.nr0;
       for (int e = tid; e < c.nRR * c.nr0; e += kThreads) Qt[e] = (T)Qa[e];
       __syncthreads();
+    }
+    if constexpr (MF == 2) {
+      qf_reorder<double>(a, c.sub, Qa, a.Qf + (int64_t)s * a.qf_slice);
+      if (kMixed)
+        qf_reorder<T>(a, c.sub, Qa, reinterpret_cast<T*>(a.Qfw) + (int64_t)s * a.qf_slice);
     }
   }
 
@@ -737,8 +1056,14 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   while (true) {
     // r = f - A x in FP64 (x and the FP64 operator); r is rounded into Vl_0
     // and W (unnormalised).  ||r||^2 and ||f||^2.
-    if constexpr (MF)
+    if constexpr (MF == 1)
       apply_slice_mfma<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd);
+    else if constexpr (MF == 2) {
+      // the product (or this workgroup's partial of it) goes through Py
+      apply_slice_mfg<double, double>(a, c, a.Qf, a.phiR, a.x, 1.0, a.Py + (int64_t)b * c.nr1);
+      if (a.S > 1) grid_sync(a.bar, target, a.wait_limit);
+      mfg_reduce<double>(a, c, c.Yd);
+    }
     else
       apply_slices<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd, fullB64);
     double rr = 0.0, ff = 0.0;
@@ -785,8 +1110,14 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     int j = 0;
     while (true) {
       T* w = Vl + (int64_t)(j + 1) * ldv;
-      if constexpr (MF)
+      if constexpr (MF == 1)
         apply_slice_mfma<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w);
+      else if constexpr (MF == 2) {
+        apply_slice_mfg<T, double>(a, c, reinterpret_cast<const T*>(a.Qfw), phiRw, W,
+                                   (T)(1.0 / nu), a.Py + (int64_t)b * c.nr1);
+        if (a.S > 1) grid_sync(a.bar, target, a.wait_limit);
+        mfg_reduce<T>(a, c, w);
+      }
       else
         apply_slices<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w, fullBw);
       // normalise V_j (its norm is known now), first-pass dots
@@ -899,12 +1230,14 @@ long long wait_limit_ticks(const DevInfo& d) {
 constexpr int kMaxDev = 64;
 std::mutex g_dev_mu;      // device queries, kernel attributes and cooperative launches
 
-const void* kernel_ptr(bool mixed, bool mf) {
+const void* kernel_ptr(bool mixed, int mode) {
   if (mixed)
-    return mf ? reinterpret_cast<const void*>(gmres_slices_kernel<float, true>)
-              : reinterpret_cast<const void*>(gmres_slices_kernel<float, false>);
-  return mf ? reinterpret_cast<const void*>(gmres_slices_kernel<double, true>)
-            : reinterpret_cast<const void*>(gmres_slices_kernel<double, false>);
+    return mode == 2   ? reinterpret_cast<const void*>(gmres_slices_kernel<float, 2>)
+           : mode == 1 ? reinterpret_cast<const void*>(gmres_slices_kernel<float, 1>)
+                       : reinterpret_cast<const void*>(gmres_slices_kernel<float, 0>);
+  return mode == 2   ? reinterpret_cast<const void*>(gmres_slices_kernel<double, 2>)
+         : mode == 1 ? reinterpret_cast<const void*>(gmres_slices_kernel<double, 1>)
+                     : reinterpret_cast<const void*>(gmres_slices_kernel<double, 0>);
 }
 
 // Device properties, and the kernels' LDS attribute raised once per device
@@ -925,8 +1258,8 @@ DevInfo dev_info() {
     TT_HIP(hipDeviceGetAttribute(&d.lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     TT_HIP(hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, dev));
     TT_REQUIRE(d.wall_khz > 0, "device reports no wall-clock rate");
-    for (int v = 0; v < 4; ++v)
-      TT_HIP(hipFuncSetAttribute(kernel_ptr(v >= 2, (v & 1) != 0),
+    for (int v = 0; v < 6; ++v)
+      TT_HIP(hipFuncSetAttribute(kernel_ptr(v >= 3, v % 3),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max - 1024));
     di[dev] = d;
     ready[dev] = true;
@@ -947,7 +1280,10 @@ int grid_cap() {
 
 struct Plan {
   int G = 0, spw = 0, m = 0, ldv = 0;
-  bool mf = false;
+  int mode = 0;          // operator application form (the kernel's MF)
+  int bt = 0;            // general matrix-core form: beta' tiles per chunk
+  int ts = 0;            // LDS room of T (doubles)
+  int S = 1;             // general matrix-core form: workgroups per slice
   size_t lds_bytes = 0;
 };
 
@@ -959,16 +1295,29 @@ bool mfma_enabled() {
   return on;
 }
 
-size_t lds_bytes_for(const KrylovShape& sh, int m, int ldv, bool mixed) {
-  const size_t dbl = (size_t)kAsDoubles + kBsDoubles + (size_t)sh.n * sh.RR * sh.r1 + ldv +
+size_t lds_bytes_for(int ts, int m, int ldv, bool mixed) {
+  const size_t dbl = (size_t)kAsDoubles + kBsDoubles + (size_t)ts + ldv +
                      (size_t)m * (m + 1) / 2 + 5 * (size_t)(m + 2) + 32;
   return dbl * sizeof(double) + (size_t)(m + 1) * ldv * (mixed ? sizeof(float) : sizeof(double));
 }
 
-// Workgroups, slices per workgroup and the restart length that fits in LDS
-// (the largest m <= restart, at least 2); G == 0 when nothing fits.  The
-// mixed kernel also needs the whole FP32 right operand of its first product
-// in LDS.
+// Largest restart length m <= mmax (at least 2) whose LDS fits, 0 if none.
+int fit_restart(int ts, int mmax, int ldv, bool mixed, size_t limit) {
+  int m = mmax;
+  while (m >= 2 && lds_bytes_for(ts, m, ldv, mixed) > limit) --m;
+  return m >= 2 ? m : 0;
+}
+
+// Workgroups, slices per workgroup, the operator application form and the
+// restart length that fits in LDS (the largest m <= restart, at least 2); G
+// == 0 when nothing fits.  One slice per workgroup takes a matrix-core form:
+// the register-resident one when n RR <= 128, n r0 <= 80 and the
+// fragment-ordered v fits in Bs, else the general (chunked) one for n <= 4,
+// r1 <= 96: with up to four workgroups per slice when the grid cap leaves room
+// and there are several chunks of 16 beta', else with the largest chunk that
+// keeps the restart length (or, when none does, the chunk that allows the
+// longest).  The vector form of the mixed
+// kernel also needs the whole FP32 right operand of its first product in LDS.
 Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mixed) {
   Plan p;
   const int cap = std::max(1, grid_cap());
@@ -976,28 +1325,57 @@ Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mix
   p.G = (sh.r0 + p.spw - 1) / p.spw;
   const int nloc = p.spw * sh.n * sh.r1;
   p.ldv = nloc + ((nloc % 2 == 0) ? 1 : 0);
-  if (mixed) {
-    const int TNf = sh.r1 <= 32 ? 32 : 64;
-    const int64_t Kp = cdiv((int64_t)sh.n * sh.r0, 16) * 16, Np = cdiv(sh.r1, TNf) * TNf;
-    if (Kp * Np * (int64_t)sizeof(float) > (int64_t)kBFull * (int64_t)sizeof(double)) {
-      p.G = 0;
-      return p;
-    }
-  }
   const size_t limit = (size_t)std::max(0, lds_limit_bytes - 1024);
-  int m = std::min(restart, kMaxRestart);
-  while (m >= 2 && lds_bytes_for(sh, m, p.ldv, mixed) > limit) --m;
-  if (m < 2) {
+  const int mmax = std::min(restart, kMaxRestart);
+  const int64_t k1 = (int64_t)sh.n * sh.r0, m1 = (int64_t)sh.n * sh.RR;
+  const int full_ts = (int)std::min<int64_t>(m1 * sh.r1, 1 << 30);
+  if (mfma_enabled() && p.spw == 1 && m1 <= 16 * 4 * kMfmaMT && k1 <= 4 * kMfmaKS &&
+      cdiv(k1, (int64_t)4) * cdiv((int64_t)sh.r1, (int64_t)16) * 64 <= kBFull) {
+    p.mode = 1;
+    p.ts = full_ts;
+    p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
+  } else if (mfma_enabled() && p.spw == 1 && sh.n <= 4 && sh.r1 <= 16 * kMfgPairs) {
+    p.mode = 2;
+    // several workgroups per slice when the grid has room: each takes every
+    // S-th chunk of 16 beta' and owns 1/S of the slice's elements
+    const int tiles = cdiv(sh.RR, 16);
+    p.S = std::max(1, std::min({4, cap / std::max(1, sh.r0), tiles}));
+    if (p.S > 1) {
+      p.G = sh.r0 * p.S;
+      const int own = cdiv(sh.n * sh.r1, p.S);
+      p.ldv = own + ((own % 2 == 0) ? 1 : 0);
+      p.bt = 1;
+      p.ts = sh.n * 16 * sh.r1;
+      p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
+    } else {
+      int best_m = 0, best_bt = 1;
+      for (int bt = mfg_bt(sh.n, sh.RR); bt >= 1; --bt) {
+        const int m = fit_restart(sh.n * 16 * bt * sh.r1, mmax, p.ldv, mixed, limit);
+        if (m > best_m) { best_m = m; best_bt = bt; }
+        if (m == mmax) break;
+      }
+      p.bt = best_bt;
+      p.ts = sh.n * 16 * p.bt * sh.r1;
+      p.m = best_m;
+    }
+  } else {
+    p.mode = 0;
+    p.ts = full_ts;
+    if (mixed) {
+      const int TNf = sh.r1 <= 32 ? 32 : 64;
+      const int64_t Kp = cdiv(k1, (int64_t)16) * 16, Np = cdiv(sh.r1, TNf) * TNf;
+      if (Kp * Np * (int64_t)sizeof(float) > (int64_t)kBFull * (int64_t)sizeof(double)) {
+        p.G = 0;
+        return p;
+      }
+    }
+    p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
+  }
+  if (p.m < 2) {
     p.G = 0;
     return p;
   }
-  p.m = m;
-  p.lds_bytes = lds_bytes_for(sh, m, p.ldv, mixed);
-  // the matrix-core kernel: one slice per workgroup,
-  // n RR <= 128, n r0 <= 80, and the fragment-ordered v fits in Bs
-  const int64_t k1 = (int64_t)sh.n * sh.r0, m1 = (int64_t)sh.n * sh.RR;
-  p.mf = mfma_enabled() && p.spw == 1 && m1 <= 16 * 4 * kMfmaMT &&
-         k1 <= 4 * kMfmaKS && cdiv(k1, (int64_t)4) * cdiv((int64_t)sh.r1, (int64_t)16) * 64 <= kBFull;
+  p.lds_bytes = lds_bytes_for(p.ts, p.m, p.ldv, mixed);
   return p;
 }
 
@@ -1005,6 +1383,15 @@ __global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict_
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
     dst[e] = (float)src[e];
+}
+
+// Doubles of the fragment-ordered Q of the general matrix-core form, at most
+// (rows padded to 16 per i, k padded to the step); zero for shapes it never
+// takes.
+int64_t qf_doubles_bound(const KrylovShape& sh) {
+  if (sh.n > 4 || sh.r1 > 16 * kMfgPairs) return 0;
+  const int64_t k1 = (int64_t)sh.n * sh.r0;
+  return (int64_t)sh.r0 * sh.n * 16 * cdiv(sh.RR, 16) * (k1 + 63);
 }
 
 }  // namespace
@@ -1031,7 +1418,9 @@ size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
   const int64_t N = (int64_t)sh.r0 * sh.n * sh.r1;
   const int cap = std::max(1, grid_cap());
   const int spw = (sh.r0 + cap - 1) / cap;
-  const int64_t G = (sh.r0 + spw - 1) / spw;
+  // workgroups: one per spw slices, or up to four per slice within the cap
+  const int64_t G = std::max<int64_t>((sh.r0 + spw - 1) / spw,
+                                      std::min<int64_t>(4 * (int64_t)sh.r0, cap));
   const int64_t m = std::min(restart, kMaxRestart);
   const int64_t nq = (int64_t)sh.r0 * sh.n * sh.RR * sh.r0 * sh.n;
   const int64_t nr = (int64_t)sh.r1 * sh.RR * sh.r1;
@@ -1040,6 +1429,10 @@ size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
   need += nq + 32;                   // Q
   need += (nq + 1) / 2 + 32;         // Q in FP32 (mixed)
   need += (nr + 1) / 2 + 32;         // PhiR in FP32 (mixed)
+  const int64_t nqf = qf_doubles_bound(sh);
+  need += nqf + 32;                  // Q in fragment order (general matrix-core form)
+  need += (nqf + 1) / 2 + 32;        // the same in FP32 (mixed)
+  need += 4 * N + 32;                // partial products of up to four workgroups per slice
   need += 2 * (G * (m + 1) + 32);    // Pd1, Pd2
   need += 2 * G + 32;                // Pn
   need += 64;                        // barrier counter
@@ -1081,6 +1474,19 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   float* q32 = reinterpret_cast<float*>(take((nq + 1) / 2));
   float* r32 = reinterpret_cast<float*>(take((nr + 1) / 2));
   a.Qw = mixed ? static_cast<void*>(q32) : static_cast<void*>(a.Q);
+  const int64_t nqf = qf_doubles_bound(sh);
+  a.Qf = take(nqf);
+  float* qf32 = reinterpret_cast<float*>(take((nqf + 1) / 2));
+  a.Qfw = mixed ? static_cast<void*>(qf32) : static_cast<void*>(a.Qf);
+  a.qf_slice = 0;
+  a.S = p.S;
+  a.Py = take(4 * N);
+  TT_REQUIRE((int64_t)p.G * sh.n * sh.r1 <= 4 * N, "Krylov solve: partial products overflow");
+  if (p.mode == 2) {
+    const int kc = mfg_kc(sh.n, p.bt, sh.r1);
+    a.qf_slice = (int64_t)sh.n * 16 * cdiv(sh.RR, 16) * ((int64_t)cdiv(sh.n * sh.r0, kc) * kc);
+    TT_REQUIRE(a.qf_slice * sh.r0 <= nqf, "Krylov solve: fragment-ordered operator overflow");
+  }
   a.phiRw = mixed ? static_cast<const void*>(r32) : static_cast<const void*>(phiR);
   a.Pd1 = take((int64_t)p.G * (p.m + 1));
   a.Pd2 = take((int64_t)p.G * (p.m + 1));
@@ -1091,6 +1497,8 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.max_iter = max_iter;
   a.spw = p.spw;
   a.ldv = p.ldv;
+  a.ts_doubles = p.ts;
+  a.mfg_bt = p.bt;
   a.tol = tol;
   a.eta = eta;
   a.inner_tol = inner_tol;
@@ -1099,7 +1507,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   TT_REQUIRE((size_t)(cur - ws) <= ws_doubles, "Krylov solve: workspace layout overflow");
 
   int per_cu = 0;
-  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_ptr(mixed, p.mf),
+  TT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_ptr(mixed, p.mode),
                                                       kThreads, p.lds_bytes));
   TT_REQUIRE((int64_t)per_cu * di.cus >= p.G, "Krylov solve: grid exceeds co-resident capacity");
 
@@ -1116,7 +1524,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   void* args[] = {&a};
   {
     std::lock_guard<std::mutex> lock(g_dev_mu);
-    TT_HIP(hipLaunchCooperativeKernel(kernel_ptr(mixed, p.mf), dim3(p.G), dim3(kThreads), args,
+    TT_HIP(hipLaunchCooperativeKernel(kernel_ptr(mixed, p.mode), dim3(p.G), dim3(kThreads), args,
                                       p.lds_bytes, s));
   }
   if (pe) g_probe->end(s);

@@ -46,7 +46,14 @@ CASES = [
     (36, 6, 2, 8, 36, 80, True),     # rank 32 + enrichment: matrix-core first product, 2592 unknowns
     (32, 4, 2, 6, 32, 80, True),     # rank 32: eight lanes per PhiR row
     (12, 4, 2, 60, 10, 30, True),    # 120 rows of Q_a: every wavefront's second m-tile
-    (41, 4, 2, 5, 9, 30, True),      # n r0 = 82 > 80: the vector-FMA first product
+    (41, 4, 2, 5, 9, 30, True),      # n r0 = 82 > 80: the general matrix-core form
+    (50, 4, 2, 10, 80, 30, True),    # r1 = 80: five n-tiles, ragged k steps of 24
+    (30, 5, 3, 50, 20, 40, False),   # n = 3, n RR = 150: four workgroups per slice
+    (20, 3, 4, 40, 24, 30, True),    # n = 4, three workgroups per slice
+    (24, 4, 2, 40, 23, 30, True),    # three workgroups per slice owning 16, 16 and 14 elements
+    (8, 4, 5, 30, 12, 30, False),    # n = 5: the vector-FMA form
+    (40, 4, 2, 8, 96, 30, True),     # r1 = 96: six n-tiles, k steps of 20
+    (8, 4, 2, 6, 100, 30, True),     # r1 = 100 > 96: the vector-FMA form
 ]
 
 
@@ -118,7 +125,8 @@ def test_persistent_gmres_iteration_limit(cuda):
 LARGE = [
     # ra, RL, n, RR, rc, restart
     (36, 56, 2, 56, 36, 80),     # the bench's rank-36 cores (matrix-core first product)
-    (64, 24, 2, 72, 64, 60),     # n r0 = 128: vector-FMA first product, 8192 unknowns
+    (64, 24, 2, 72, 64, 60),     # n r0 = 128: general matrix-core form, 8192 unknowns
+    (48, 40, 2, 200, 48, 60),    # operator rank 200: 13 chunks of 16 beta' over four workgroups
 ]
 
 
