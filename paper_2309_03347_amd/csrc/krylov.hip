@@ -65,7 +65,7 @@ struct SArgs {
   double* Pn;           // G x 2
   int m, max_iter, spw, ldv;
   int ts_doubles;       // LDS room of the first product's T (doubles)
-  int mfg_bt;           // general matrix-core form: beta' tiles of 16 per chunk
+  int mfg_bc;           // general matrix-core form: beta' per sub-chunk
   double tol, eta;
   double inner_tol;     // mixed mode: an inner cycle stops at this fraction of its start residual
   unsigned* bar;        // grid barrier: count, epoch flag (+32), abort word (+48)
@@ -603,22 +603,29 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const E* Qe, cons
 
 // The general matrix-core form's second product: y[i][c] (+)= sum_{k < K}
 // T[i][k] PhiR[c][k] with T rows of length K in LDS (row i at Ts + i K) and
-// PhiR rows starting at phiRe (row stride K3).  A wavefront takes four rows c
-// at a time with its lanes along k (16-byte loads of two consecutive
-// elements when the rows are aligned), so every load of PhiR uses whole cache
-// lines and each T value read from LDS serves four rows; the 64 lanes' sums are
-// added by a butterfly.
+// PhiR rows starting at phiRe (row stride K3).  Each wavefront owns a quarter
+// of the rows c and takes them in equal passes of at most kS3Rows, its lanes
+// along k (16-byte loads when the rows are aligned): every load of PhiR uses
+// whole cache lines, each T value read from LDS serves the pass's rows, and
+// one pass over k keeps that many loads per lane in flight.  The 64 lanes'
+// sums are added by butterflies at the end of the pass.
+constexpr int kS3Rows = 8;
+
 template <typename E, typename O>
 __device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K, const E* Ts,
                             O* ys, bool accum) {
-  constexpr int CR = 4;
-  typedef E V2 __attribute__((ext_vector_type(2)));
+  constexpr int CR = kS3Rows;
+  constexpr int W = 16 / (int)sizeof(E);     // elements per 16-byte load
+  typedef E VW __attribute__((ext_vector_type(W)));
   const int w = c.tid >> 6, l = c.lane, n = a.n, r1 = a.r1;
   const int64_t K3 = c.K3;
-  const bool vec = (K % 2 == 0) && (K3 % 2 == 0) &&
-                   ((reinterpret_cast<uintptr_t>(phiRe) & (2 * sizeof(E) - 1)) == 0);
-  for (int c0 = CR * w; c0 < r1; c0 += 4 * CR) {
-    const int nr = min(CR, r1 - c0);
+  const bool vec = (K % W == 0) && (K3 % W == 0) &&
+                   ((reinterpret_cast<uintptr_t>(phiRe) & 15) == 0);
+  // wavefront w takes rows [w rpw, (w + 1) rpw) in equal passes of at most CR
+  const int rpw = cdiv(r1, 4), np = cdiv(rpw, CR), rpp = cdiv(rpw, np);
+  const int rw1 = min(r1, (w + 1) * rpw);
+  for (int c0 = w * rpw; c0 < rw1; c0 += rpp) {
+    const int nr = min(rpp, rw1 - c0);
     for (int i0 = 0; i0 < n; i0 += 2) {
       const bool two = i0 + 1 < n;
       double acc[CR][2];
@@ -627,53 +634,31 @@ __device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K,
       const E* t0 = Ts + (int64_t)i0 * K;
       const E* t1 = two ? t0 + K : t0;
       if (vec) {
-        const int K2 = K / 2;
-        const V2* ta = reinterpret_cast<const V2*>(t0);
-        const V2* tb = reinterpret_cast<const V2*>(t1);
-        const V2* prow[CR];
+        const int KW = K / W;
+        const VW* ta = reinterpret_cast<const VW*>(t0);
+        const VW* tb = reinterpret_cast<const VW*>(t1);
+        const VW* p0 = reinterpret_cast<const VW*>(phiRe + (int64_t)c0 * K3);
+        const int64_t rs = K3 / W;     // row stride in loads
+#pragma unroll (W == 2 ? 2 : 1)
+        for (int k = l; k < KW; k += 64) {
+          VW pv[CR];
 #pragma unroll
-        for (int r = 0; r < CR; ++r)
-          prow[r] = reinterpret_cast<const V2*>(phiRe + (int64_t)(c0 + min(r, nr - 1)) * K3);
-        constexpr int U = 4;   // k positions per lane in flight: U CR 16-byte loads
-        int k = l;
-        for (; k + 64 * (U - 1) < K2; k += 64 * U) {
-          V2 pv[U][CR], x0[U], x1[U];
+          for (int r = 0; r < CR; ++r) pv[r] = p0[(int64_t)min(r, nr - 1) * rs + k];
+          const VW x0 = ta[k], x1 = tb[k];
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+          for (int r = 0; r < CR; ++r)
 #pragma unroll
-            for (int r = 0; r < CR; ++r) pv[u][r] = prow[r][k + 64 * u];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            x0[u] = ta[k + 64 * u];
-            x1[u] = tb[k + 64 * u];
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < CR; ++r) {
-              acc[r][0] = fma((double)x0[u].x, (double)pv[u][r].x, acc[r][0]);
-              acc[r][0] = fma((double)x0[u].y, (double)pv[u][r].y, acc[r][0]);
-              acc[r][1] = fma((double)x1[u].x, (double)pv[u][r].x, acc[r][1]);
-              acc[r][1] = fma((double)x1[u].y, (double)pv[u][r].y, acc[r][1]);
+            for (int h = 0; h < W; ++h) {
+              acc[r][0] = fma((double)x0[h], (double)pv[r][h], acc[r][0]);
+              acc[r][1] = fma((double)x1[h], (double)pv[r][h], acc[r][1]);
             }
-        }
-        for (; k < K2; k += 64) {
-          const V2 x0 = ta[k], x1 = tb[k];
-#pragma unroll
-          for (int r = 0; r < CR; ++r) {
-            const V2 pv = prow[r][k];
-            acc[r][0] = fma((double)x0.x, (double)pv.x, acc[r][0]);
-            acc[r][0] = fma((double)x0.y, (double)pv.y, acc[r][0]);
-            acc[r][1] = fma((double)x1.x, (double)pv.x, acc[r][1]);
-            acc[r][1] = fma((double)x1.y, (double)pv.y, acc[r][1]);
-          }
         }
       } else {
         for (int k = l; k < K; k += 64) {
           const E x0 = t0[k], x1 = t1[k];
 #pragma unroll
           for (int r = 0; r < CR; ++r) {
-            const E p = r < nr ? phiRe[(int64_t)(c0 + r) * K3 + k] : E(0);
+            const E p = phiRe[(int64_t)(c0 + min(r, nr - 1)) * K3 + k];
             acc[r][0] = fma((double)x0, (double)p, acc[r][0]);
             acc[r][1] = fma((double)x1, (double)p, acc[r][1]);
           }
@@ -685,11 +670,15 @@ __device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K,
         acc[r][1] = wave_sum(acc[r][1]);
       }
       if (l == 0) {
-        for (int r = 0; r < nr; ++r)
-          for (int q = 0; q < (two ? 2 : 1); ++q) {
-            O* o = ys + (int64_t)(i0 + q) * r1 + c0 + r;
-            const O v = (O)acc[r][q];
-            *o = accum ? *o + v : v;
+#pragma unroll
+        for (int r = 0; r < CR; ++r)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            if (r < nr && (q == 0 || two)) {
+              O* o = ys + (int64_t)(i0 + q) * r1 + c0 + r;
+              const O v = (O)acc[r][q];
+              *o = accum ? *o + v : v;
+            }
           }
       }
     }
@@ -698,58 +687,80 @@ __device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K,
 }
 
 // General matrix-core form for one slice per workgroup, any n RR and n r0
-// (n <= 4, r1 <= 96).  The rows (i, beta') of Q_a are taken in chunks that
-// hold the same range of 16 bt beta' for every i (at most 64 rows), so each
-// chunk's part of the second product reads one range of every PhiR row.  The
-// first product of a chunk runs over k in steps of KC: the chunk's rows of
+// (n <= 4, r1 <= 96).  The slice's beta' are split into S contiguous ranges
+// of q = ceil(RR / S), one per workgroup of the slice, and a range is taken in
+// sub-chunks of at most bc beta'.  A sub-chunk's rows (i, beta') of Q_a are
+// packed densely, row i bc + (beta' - b0), into m-tiles of 16, so each
+// sub-chunk's part of the second product reads one range of every PhiR row.
+// The first product of a sub-chunk runs over k in steps of KC: its rows of
 // Q_a (into As, from a copy laid out in fragment order once per solve, see
 // qf_reorder) and KC rows of v (into Bs) are staged in fragment order, the
 // next step's values loaded into registers while the current one is
 // multiplied; wavefront w owns the (m-tile, n-tile) pairs w, w + 4, ... and
-// keeps their accumulators over the k steps.  The chunk's T goes to Ts and
-// its part of the second product is added to out.  With S workgroups per
-// slice each takes every S-th chunk and writes its partial product; the sum
-// of the S partials is formed after a grid barrier (mfg_reduce).
+// keeps their accumulators over the k steps.  The sub-chunk's T goes to Ts
+// and its part of the second product is added to out.  With S > 1 out is the
+// workgroup's partial product; the sum of the S partials is formed after a
+// grid barrier (mfg_reduce).
 constexpr int kMfgPairs = 6;     // (m-tile, n-tile) pairs per wavefront: 4 m-tiles x 6 n-tiles
-constexpr int kMfgRows = 64;     // rows of Q_a per chunk
+constexpr int kMfgTiles = 4;     // m-tiles per sub-chunk, at most
 
-__host__ __device__ inline int mfg_bt(int n, int RR) {
-  const int bt = kMfgRows / (16 * n);
-  const int need = (RR + 15) / 16;
-  return bt < need ? bt : need;
-}
-__host__ __device__ inline int mfg_kc(int n, int bt, int r1) {
-  // k-steps of 4 per stage: the chunk's A fragments and v's fragments each fit
-  // 2048 elements (eight per thread)
+struct MfgGeom {
+  int q, rb0, rb1;     // beta' per workgroup, the workgroup's range
+  int bc, MTmax;       // beta' per sub-chunk, its m-tiles at most
+  int KS, KC, nkc;     // k-steps of 4 per stage, k per stage, stages
+  int nsc;             // sub-chunks per range
+  int64_t sc_size;     // elements of a sub-chunk's fragments over all stages
+};
+
+__host__ __device__ inline MfgGeom mfg_geom(int n, int r0, int RR, int r1, int S, int bc,
+                                            int sub) {
+  MfgGeom g;
+  g.q = (RR + S - 1) / S;
+  g.rb0 = sub * g.q < RR ? sub * g.q : RR;
+  g.rb1 = g.rb0 + g.q < RR ? g.rb0 + g.q : RR;
+  g.bc = bc;
+  g.MTmax = (n * bc + 15) / 16;
   const int nt = (r1 + 15) / 16;
-  int ks = 32 / (n * bt);
+  // the sub-chunk's A fragments and v's fragments each fit 2048 elements
+  // (eight per thread) per stage
+  int ks = 32 / g.MTmax;
   if (32 / nt < ks) ks = 32 / nt;
   if (ks > 16) ks = 16;
-  return 4 * ks;
+  g.KS = ks;
+  g.KC = 4 * ks;
+  g.nkc = (n * r0 + g.KC - 1) / g.KC;
+  g.nsc = (g.q + bc - 1) / bc;
+  g.sc_size = (int64_t)g.MTmax * 16 * g.nkc * g.KC;
+  return g;
 }
 
 // Q_a (row-major, n RR x K1) into the general matrix-core form's order: for
-// each chunk of beta' (16 BT at a time) and each k step of KC, the chunk's
+// each of the workgroup's sub-chunks and each k step of KC, the sub-chunk's
 // fragments (m-tile, k-step) of 64 lanes, lane l holding A[l % 16][l / 16] of
-// its fragment, zero past the rows and columns.  Once per solve, by the
-// workgroup that owns the slice (with S > 1, each of the slice's workgroups
-// for its own chunks).
+// its fragment, zero past the rows and columns; sub-chunk j of workgroup sub
+// starts at (sub nsc + j) sc_size.  Once per solve, each workgroup for its own
+// range.
 template <typename E>
 __device__ void qf_reorder(const SArgs& a, int sub, const double* Qa, E* Qs) {
-  const int K1 = a.n * a.r0, RR = a.RR, n = a.n, BT = a.mfg_bt;
-  const int KC = mfg_kc(n, BT, a.r1), KS = KC / 4, nkc = cdiv(K1, KC);
-  const int64_t full = (int64_t)n * BT * KS * 64 * nkc;
-  for (int64_t f = threadIdx.x; f < a.qf_slice; f += kThreads) {
-    const int ci = (int)(f / full);
-    if (ci % a.S != sub) continue;      // another workgroup's chunk
-    const int64_t rem = f - ci * full;
-    const int b0 = 16 * BT * ci, bc = min(16 * BT, RR - b0), tpi = cdiv(bc, 16);
-    const int per = n * tpi * KS * 64;
-    const int j = (int)(rem / per), e = (int)(rem - (int64_t)j * per);
-    const int frag = e >> 6, ln = e & 63, mt = frag / KS, ks = frag - mt * KS;
-    const int i = mt / tpi, bp = 16 * (mt - i * tpi) + (ln & 15);
-    const int kk = j * KC + 4 * ks + (ln >> 4);
-    Qs[f] = (bp < bc && kk < K1) ? (E)Qa[(int64_t)(i * RR + b0 + bp) * K1 + kk] : E(0);
+  const int K1 = a.n * a.r0, RR = a.RR, n = a.n;
+  const MfgGeom g = mfg_geom(n, a.r0, RR, a.r1, a.S, a.mfg_bc, sub);
+  for (int j = 0; j < g.nsc; ++j) {
+    const int b0 = g.rb0 + j * g.bc;
+    if (b0 >= g.rb1) break;
+    const int bc = min(g.bc, g.rb1 - b0), rows = n * bc;
+    const int na = cdiv(rows, 16) * g.KS * 64;
+    E* Qj = Qs + (int64_t)(sub * g.nsc + j) * g.sc_size;
+    for (int64_t f = threadIdx.x; f < (int64_t)g.nkc * na; f += kThreads) {
+      const int st = (int)(f / na), e = (int)(f - (int64_t)st * na);
+      const int frag = e >> 6, ln = e & 63, mt = frag / g.KS, ks = frag - mt * g.KS;
+      const int rho = 16 * mt + (ln & 15), kk = st * g.KC + 4 * ks + (ln >> 4);
+      E val = E(0);
+      if (rho < rows && kk < K1) {
+        const int i = rho / bc, bp = rho - i * bc;
+        val = (E)Qa[(int64_t)(i * RR + b0 + bp) * K1 + kk];
+      }
+      Qj[f] = val;
+    }
   }
   __syncthreads();
 }
@@ -762,30 +773,30 @@ __device__ void apply_slice_mfg(const SArgs& a, const Ctx& c, const E* Qfe, cons
   const int tid = c.tid, l = c.lane, w = tid >> 6;
   const int K1 = c.nr0, RR = a.RR, n = a.n, r1 = a.r1;
   const int NT = cdiv(r1, 16);
-  const int BT = a.mfg_bt, KC = mfg_kc(n, BT, r1), KS = KC / 4;
+  const MfgGeom g = mfg_geom(n, a.r0, RR, r1, a.S, a.mfg_bc, c.sub);
+  const int KC = g.KC, KS = g.KS;
   E* As = reinterpret_cast<E*>(c.As);
   E* Bs = reinterpret_cast<E*>(c.Bs);
   E* Ts = reinterpret_cast<E*>(c.Ts);
-  const int nkc = cdiv(K1, KC);
   const E* Qs = Qfe + (int64_t)c.a0 * a.qf_slice;
-  // staging: A chunk (MT m-tiles x KS k-steps fragments) and B (KS x NT fragments),
-  // at most 8 + 8 elements per thread and step
+  // staging: A (MT m-tiles x KS k-steps fragments) and B (KS x NT fragments),
+  // at most 8 + 8 elements per thread and stage
   constexpr int kSA = 8, kSB = 8;
-  // with S > 1 the workgroup takes chunks sub, sub + S, ... and out is its
-  // partial product (zero when it has no chunk)
-  if (16 * BT * c.sub >= RR) {
+  if (g.rb0 >= g.rb1) {
+    // no beta' for this workgroup: its partial product is zero
     for (int e = tid; e < n * r1; e += kThreads) out[e] = O(0);
     __syncthreads();
   }
-  for (int b0 = 16 * BT * c.sub; b0 < RR; b0 += 16 * BT * a.S) {
-    const int bc = min(16 * BT, RR - b0);      // beta' rows of the chunk, for every i
-    const int tpi = cdiv(bc, 16);
-    const int MT = n * tpi;                    // m-tiles of the chunk
+  for (int j = 0; j < g.nsc; ++j) {
+    const int b0 = g.rb0 + j * g.bc;
+    if (b0 >= g.rb1) break;
+    const int bc = min(g.bc, g.rb1 - b0);     // beta' of the sub-chunk, for every i
+    const int rows = n * bc;
+    const int MT = cdiv(rows, 16);
     const int npairs = MT * NT;
     const int na = MT * KS * 64, nbv = KS * NT * 64;
     E ra[kSA], rb[kSB];
-    // the chunk's fragments of the k step starting at K0, consecutive in Qf
-    const E* Qc = Qs + (int64_t)(b0 / 16) * n * KS * 64 * nkc;
+    const E* Qc = Qs + (int64_t)(c.sub * g.nsc + j) * g.sc_size;
     auto load = [&](int K0) {
       const E* Qk = Qc + (int64_t)(K0 / KC) * na;
 #pragma unroll
@@ -799,8 +810,8 @@ __device__ void apply_slice_mfg(const SArgs& a, const Ctx& c, const E* Qfe, cons
         E val = E(0);
         if (e < nbv) {
           const int frag = e >> 6, ln = e & 63, ks = frag / NT, nt = frag - ks * NT;
-          const int kk = K0 + 4 * ks + (ln >> 4), j = 16 * nt + (ln & 15);
-          if (kk < K1 && j < r1) val = ld_coh<E>(v + (int64_t)kk * r1 + j);
+          const int kk = K0 + 4 * ks + (ln >> 4), jj = 16 * nt + (ln & 15);
+          if (kk < K1 && jj < r1) val = ld_coh<E>(v + (int64_t)kk * r1 + jj);
         }
         rb[u] = val;
       }
@@ -833,25 +844,24 @@ __device__ void apply_slice_mfg(const SArgs& a, const Ctx& c, const E* Qfe, cons
         }
       }
     }
-    // the chunk's T: Ts[(i bc + beta' - b0) r1 + d]
+    // the sub-chunk's T, row i bc + (beta' - b0): Ts[rho r1 + d]
 #pragma unroll
-    for (int q = 0; q < kMfgPairs; ++q) {
-      const int pr = w + 4 * q;
+    for (int qq = 0; qq < kMfgPairs; ++qq) {
+      const int pr = w + 4 * qq;
       if (pr < npairs) {
         const int mt = pr / NT, nt = pr - mt * NT;
-        const int i = mt / tpi, bt = mt - i * tpi;
         const int col = 16 * nt + (l & 15);
         if (col < r1) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int bp = 16 * bt + Ops::row(l, r);
-            if (bp < bc) Ts[(int64_t)(i * bc + bp) * r1 + col] = alpha * acc[q][r];
+            const int rho = 16 * mt + Ops::row(l, r);
+            if (rho < rows) Ts[(int64_t)rho * r1 + col] = alpha * acc[qq][r];
           }
         }
       }
     }
     __syncthreads();
-    stage3_rows<E, O>(a, c, phiRe + (int64_t)b0 * r1, bc * r1, Ts, out, b0 > 16 * BT * c.sub);
+    stage3_rows<E, O>(a, c, phiRe + (int64_t)b0 * r1, bc * r1, Ts, out, j > 0);
   }
 }
 
@@ -947,14 +957,13 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   for (int s = c.a0; s < c.a1; ++s) {
     double* Qa = a.Q + (int64_t)s * c.nRR * c.nr0;
     if (MF == 2 && a.S > 1) {
-      // only the rows (i, beta') of the workgroup's own chunks
-      const int bstep = 16 * a.mfg_bt;
-      for (int b0 = bstep * c.sub; b0 < a.RR; b0 += bstep * a.S) {
-        const int bc = min(bstep, a.RR - b0);
+      // only the rows (i, beta') of the workgroup's own beta' range
+      const MfgGeom g = mfg_geom(a.n, a.r0, a.RR, a.r1, a.S, a.mfg_bc, c.sub);
+      if (g.rb1 > g.rb0) {
         for (int i = 0; i < a.n; ++i) {
-          const int64_t row0 = (int64_t)i * a.RR + b0;
+          const int64_t row0 = (int64_t)i * a.RR + g.rb0;
           for (int j = 0; j < a.n; ++j)
-            wg_gemm<false>(bc, a.r0, a.RL, 1.0,
+            wg_gemm<false>(g.rb1 - g.rb0, a.r0, a.RL, 1.0,
                            Strided{a.Ap + row0 * a.RL * a.n + j, (int64_t)a.RL * a.n, a.n},
                            Strided{a.phiL + (int64_t)s * a.RL * a.r0, a.r0, 1},
                            Qa + row0 * c.nr0 + j, c.nr0, a.n, c.As, c.Bs);
@@ -1281,7 +1290,7 @@ int grid_cap() {
 struct Plan {
   int G = 0, spw = 0, m = 0, ldv = 0;
   int mode = 0;          // operator application form (the kernel's MF)
-  int bt = 0;            // general matrix-core form: beta' tiles per chunk
+  int bc = 0;            // general matrix-core form: beta' per sub-chunk
   int ts = 0;            // LDS room of T (doubles)
   int S = 1;             // general matrix-core form: workgroups per slice
   size_t lds_bytes = 0;
@@ -1301,6 +1310,15 @@ size_t lds_bytes_for(int ts, int m, int ldv, bool mixed) {
   return dbl * sizeof(double) + (size_t)(m + 1) * ldv * (mixed ? sizeof(float) : sizeof(double));
 }
 
+// Workgroups per slice S and beta' per sub-chunk of the general matrix-core
+// form: up to four workgroups per slice within the grid cap, each with at
+// least eight beta', and sub-chunks of at most 64 rows (n bc <= 64).
+void mfg_split(const KrylovShape& sh, int cap, int& S, int& bc) {
+  S = std::max(1, std::min({4, cap / std::max(1, sh.r0), std::max(1, sh.RR / 8)}));
+  const int q = cdiv(sh.RR, S);
+  bc = std::max(1, std::min(64 / sh.n, q));
+}
+
 // Largest restart length m <= mmax (at least 2) whose LDS fits, 0 if none.
 int fit_restart(int ts, int mmax, int ldv, bool mixed, size_t limit) {
   int m = mmax;
@@ -1312,11 +1330,8 @@ int fit_restart(int ts, int mmax, int ldv, bool mixed, size_t limit) {
 // restart length that fits in LDS (the largest m <= restart, at least 2); G
 // == 0 when nothing fits.  One slice per workgroup takes a matrix-core form:
 // the register-resident one when n RR <= 128, n r0 <= 80 and the
-// fragment-ordered v fits in Bs, else the general (chunked) one for n <= 4,
-// r1 <= 96: with up to four workgroups per slice when the grid cap leaves room
-// and there are several chunks of 16 beta', else with the largest chunk that
-// keeps the restart length (or, when none does, the chunk that allows the
-// longest).  The vector form of the mixed
+// fragment-ordered v fits in Bs, else the general one for n <= 4, r1 <= 96
+// (mfg_split).  The vector form of the mixed
 // kernel also needs the whole FP32 right operand of its first product in LDS.
 Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mixed) {
   Plan p;
@@ -1336,28 +1351,12 @@ Plan make_plan(const KrylovShape& sh, int restart, int lds_limit_bytes, bool mix
     p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
   } else if (mfma_enabled() && p.spw == 1 && sh.n <= 4 && sh.r1 <= 16 * kMfgPairs) {
     p.mode = 2;
-    // several workgroups per slice when the grid has room: each takes every
-    // S-th chunk of 16 beta' and owns 1/S of the slice's elements
-    const int tiles = cdiv(sh.RR, 16);
-    p.S = std::max(1, std::min({4, cap / std::max(1, sh.r0), tiles}));
-    if (p.S > 1) {
-      p.G = sh.r0 * p.S;
-      const int own = cdiv(sh.n * sh.r1, p.S);
-      p.ldv = own + ((own % 2 == 0) ? 1 : 0);
-      p.bt = 1;
-      p.ts = sh.n * 16 * sh.r1;
-      p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
-    } else {
-      int best_m = 0, best_bt = 1;
-      for (int bt = mfg_bt(sh.n, sh.RR); bt >= 1; --bt) {
-        const int m = fit_restart(sh.n * 16 * bt * sh.r1, mmax, p.ldv, mixed, limit);
-        if (m > best_m) { best_m = m; best_bt = bt; }
-        if (m == mmax) break;
-      }
-      p.bt = best_bt;
-      p.ts = sh.n * 16 * p.bt * sh.r1;
-      p.m = best_m;
-    }
+    mfg_split(sh, cap, p.S, p.bc);
+    p.G = sh.r0 * p.S;
+    const int own = cdiv(sh.n * sh.r1, p.S);
+    p.ldv = own + ((own % 2 == 0) ? 1 : 0);
+    p.ts = sh.n * p.bc * sh.r1;
+    p.m = fit_restart(p.ts, mmax, p.ldv, mixed, limit);
   } else {
     p.mode = 0;
     p.ts = full_ts;
@@ -1385,13 +1384,14 @@ __global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict_
     dst[e] = (float)src[e];
 }
 
-// Doubles of the fragment-ordered Q of the general matrix-core form, at most
-// (rows padded to 16 per i, k padded to the step); zero for shapes it never
-// takes.
-int64_t qf_doubles_bound(const KrylovShape& sh) {
-  if (sh.n > 4 || sh.r1 > 16 * kMfgPairs) return 0;
-  const int64_t k1 = (int64_t)sh.n * sh.r0;
-  return (int64_t)sh.r0 * sh.n * 16 * cdiv(sh.RR, 16) * (k1 + 63);
+// Doubles of the fragment-ordered Q of the general matrix-core form for this
+// shape and grid cap (zero for shapes it never takes).
+int64_t qf_doubles(const KrylovShape& sh, int cap) {
+  if (sh.n > 4 || sh.r1 > 16 * kMfgPairs || sh.r0 > cap) return 0;
+  int S = 1, bc = 1;
+  mfg_split(sh, cap, S, bc);
+  const MfgGeom g = mfg_geom(sh.n, sh.r0, sh.RR, sh.r1, S, bc, 0);
+  return (int64_t)sh.r0 * S * g.nsc * g.sc_size;
 }
 
 }  // namespace
@@ -1429,7 +1429,7 @@ size_t krylov_ws_doubles(const KrylovShape& sh, int restart, int /*grid*/) {
   need += nq + 32;                   // Q
   need += (nq + 1) / 2 + 32;         // Q in FP32 (mixed)
   need += (nr + 1) / 2 + 32;         // PhiR in FP32 (mixed)
-  const int64_t nqf = qf_doubles_bound(sh);
+  const int64_t nqf = qf_doubles(sh, cap);
   need += nqf + 32;                  // Q in fragment order (general matrix-core form)
   need += (nqf + 1) / 2 + 32;        // the same in FP32 (mixed)
   need += 4 * N + 32;                // partial products of up to four workgroups per slice
@@ -1474,7 +1474,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   float* q32 = reinterpret_cast<float*>(take((nq + 1) / 2));
   float* r32 = reinterpret_cast<float*>(take((nr + 1) / 2));
   a.Qw = mixed ? static_cast<void*>(q32) : static_cast<void*>(a.Q);
-  const int64_t nqf = qf_doubles_bound(sh);
+  const int64_t nqf = qf_doubles(sh, std::max(1, grid_cap()));
   a.Qf = take(nqf);
   float* qf32 = reinterpret_cast<float*>(take((nqf + 1) / 2));
   a.Qfw = mixed ? static_cast<void*>(qf32) : static_cast<void*>(a.Qf);
@@ -1483,8 +1483,8 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.Py = take(4 * N);
   TT_REQUIRE((int64_t)p.G * sh.n * sh.r1 <= 4 * N, "Krylov solve: partial products overflow");
   if (p.mode == 2) {
-    const int kc = mfg_kc(sh.n, p.bt, sh.r1);
-    a.qf_slice = (int64_t)sh.n * 16 * cdiv(sh.RR, 16) * ((int64_t)cdiv(sh.n * sh.r0, kc) * kc);
+    const MfgGeom g = mfg_geom(sh.n, sh.r0, sh.RR, sh.r1, p.S, p.bc, 0);
+    a.qf_slice = (int64_t)p.S * g.nsc * g.sc_size;
     TT_REQUIRE(a.qf_slice * sh.r0 <= nqf, "Krylov solve: fragment-ordered operator overflow");
   }
   a.phiRw = mixed ? static_cast<const void*>(r32) : static_cast<const void*>(phiR);
@@ -1498,7 +1498,7 @@ bool krylov_solve(hipStream_t s, const KrylovShape& sh, const double* phiL, cons
   a.spw = p.spw;
   a.ldv = p.ldv;
   a.ts_doubles = p.ts;
-  a.mfg_bt = p.bt;
+  a.mfg_bc = p.bc;
   a.tol = tol;
   a.eta = eta;
   a.inner_tol = inner_tol;
