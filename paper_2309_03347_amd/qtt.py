@@ -312,7 +312,7 @@ def tt_svd(tensor: np.ndarray, tol: float = 1e-14) -> Cores:
     rest = tensor.reshape(1, -1)
     for k in range(d - 1):
         mat = rest.reshape(r * shape[k], -1)
-        u, s, vt = np.linalg.svd(mat, full_matrices=False)
+        u, s, vt = _svd(mat)
         tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]
         keep = max(1, int(np.sum(tail > delta)))
         cores.append(u[:, :keep].reshape(r, shape[k], keep))
@@ -335,6 +335,16 @@ def _from_vec(vec: Cores, shapes) -> Cores:
     return out
 
 
+def _svd(m: np.ndarray):
+    """Thin SVD; LAPACK's divide-and-conquer driver can fail to converge on
+    some matrices, then the QR-iteration driver is used."""
+    try:
+        return np.linalg.svd(m, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
+
+
 def tt_round_host(cores: Cores, tol: float, rmax: int = 1 << 30) -> Cores:
     """TT rounding on the host (operator setup only): left-to-right QR
     orthogonalization, then right-to-left truncated SVD with the threshold
@@ -354,7 +364,7 @@ def tt_round_host(cores: Cores, tol: float, rmax: int = 1 << 30) -> Cores:
     delta = tol * nrm / np.sqrt(d - 1)
     for k in range(d - 1, 0, -1):
         r0, n, r1 = vec[k].shape
-        u, s, vt = np.linalg.svd(vec[k].reshape(r0, n * r1), full_matrices=False)
+        u, s, vt = _svd(vec[k].reshape(r0, n * r1))
         tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]
         keep = max(1, min(rmax, int(np.sum(tail > delta))))
         vec[k] = vt[:keep].reshape(keep, n, r1)
