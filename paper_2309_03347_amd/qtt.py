@@ -359,7 +359,8 @@ def tt_round_host(cores: Cores, tol: float, rmax: int = 1 << 30) -> Cores:
         r0, n, r1 = vec[k].shape
         q, rr = np.linalg.qr(vec[k].reshape(r0 * n, r1))
         vec[k] = q.reshape(r0, n, q.shape[1])
-        vec[k + 1] = np.einsum("ab,bnc->anc", rr, vec[k + 1])
+        b, n1, c1 = vec[k + 1].shape
+        vec[k + 1] = (rr @ vec[k + 1].reshape(b, n1 * c1)).reshape(rr.shape[0], n1, c1)
     nrm = np.linalg.norm(vec[-1])
     delta = tol * nrm / np.sqrt(d - 1)
     for k in range(d - 1, 0, -1):
@@ -368,5 +369,7 @@ def tt_round_host(cores: Cores, tol: float, rmax: int = 1 << 30) -> Cores:
         tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]
         keep = max(1, min(rmax, int(np.sum(tail > delta))))
         vec[k] = vt[:keep].reshape(keep, n, r1)
-        vec[k - 1] = np.einsum("anb,bc->anc", vec[k - 1], u[:, :keep] * s[:keep])
+        a0, n0, b0 = vec[k - 1].shape
+        vec[k - 1] = (vec[k - 1].reshape(a0 * n0, b0) @ (u[:, :keep] * s[:keep])).reshape(
+            a0, n0, keep)
     return _from_vec(vec, shapes)
