@@ -255,7 +255,8 @@ tt_status ttnt_release(void);
  *   3. psi+ rounded to (tol, rmax);
  *   4. k+ = k * <cF, psi+> / <cF, psi>; psi+ scaled to unit 2-norm.
  * The solver copies all problem data to device memory it allocates at
- * creation (hipMalloc happens only in tt_solver_create).
+ * creation (hipMalloc happens only in tt_solver_create), or to a workspace
+ * the caller owns (tt_solver_workspace_size, tt_solver_create_in).
  */
 typedef struct {
   tt_mat H;
@@ -307,6 +308,25 @@ typedef struct tt_solver_s tt_solver;
 
 tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
                            tt_solver** out);
+/*
+ * tt_solver_workspace_size - device bytes the solver of `problem` and `opts`
+ * needs (the working copies of H, S + F/k, psi and its interfaces, the AMEn
+ * and Z trains, the local-solve and rounding scratch, all sized for the rank
+ * caps).  Reads the problem's cores from device memory (synchronous);
+ * allocates nothing.  TT_E_ARG on a bad descriptor or option.
+ *
+ * tt_solver_create_in - tt_solver_create on a caller-owned device workspace
+ * of at least that many bytes, 256-byte aligned: the solver makes no device
+ * allocation and borrows the workspace until tt_solver_destroy (which does
+ * not free it; the caller frees it afterwards).  Its pinned host readback
+ * area (6 d + 32 doubles) and one HIP event are still created.
+ * TT_E_CAPACITY if workspace_bytes is smaller than the query's answer,
+ * TT_E_ARG if the workspace is NULL or misaligned.
+ */
+tt_status tt_solver_workspace_size(const tt_problem* problem, const tt_solver_opts* opts,
+                                   size_t* bytes);
+tt_status tt_solver_create_in(const tt_problem* problem, const tt_solver_opts* opts,
+                              void* workspace, size_t workspace_bytes, tt_solver** out);
 tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);
 /*
  * tt_amen_mv - approximate TT matrix-vector product y ~ A x with y's ranks

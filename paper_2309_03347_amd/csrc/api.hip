@@ -342,23 +342,55 @@ tt_status ttnt_set_grid_wait_limit(double seconds) {
   });
 }
 
-tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
-                           tt_solver** out) {
+namespace {
+
+void check_problem(const tt_problem* problem) {
+  check_mat(&problem->H, "H");
+  check_mat(&problem->SF, "SF");
+  check_vec(&problem->cF, "cF");
+  check_vec(&problem->psi0, "psi0");
+}
+
+tt_status solver_create(const tt_problem* problem, const tt_solver_opts* opts, void* ws,
+                        size_t ws_bytes, tt_solver** out) {
   return guard([&] {
     TT_REQUIRE(problem && opts && out, "NULL argument");
-    check_mat(&problem->H, "H");
-    check_mat(&problem->SF, "SF");
-    check_vec(&problem->cF, "cF");
-    check_vec(&problem->psi0, "psi0");
+    check_problem(problem);
     auto* s = new tt_solver_s();
     try {
-      s->impl.create(problem, opts);
+      s->impl.create(problem, opts, ws, ws_bytes);
     } catch (...) {
       delete s;
       throw;
     }
     *out = s;
   });
+}
+
+}  // namespace
+
+tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts,
+                           tt_solver** out) {
+  return solver_create(problem, opts, nullptr, 0, out);
+}
+
+tt_status tt_solver_workspace_size(const tt_problem* problem, const tt_solver_opts* opts,
+                                   size_t* bytes) {
+  return guard([&] {
+    TT_REQUIRE(problem && opts && bytes, "NULL argument");
+    check_problem(problem);
+    Solver probe_only;
+    probe_only.create(problem, opts, nullptr, 0, bytes);
+  });
+}
+
+tt_status tt_solver_create_in(const tt_problem* problem, const tt_solver_opts* opts,
+                              void* workspace, size_t workspace_bytes, tt_solver** out) {
+  if (!workspace) {
+    g_err = "workspace is NULL";
+    return TT_E_ARG;
+  }
+  return solver_create(problem, opts, workspace, workspace_bytes, out);
 }
 
 tt_status tt_amen_mv(const tt_mat* A, const tt_vec* x, tt_vec* y, double tol, int32_t rmax,

@@ -45,6 +45,7 @@ struct Solver {
 
   void* mem = nullptr;
   size_t mem_bytes = 0;
+  bool owns_mem = true;        // false when the caller supplied the workspace
 
   TTm H, SF, Id, Ak;
   double *Hc = nullptr, *SFc = nullptr, *F0 = nullptr, *A0 = nullptr, *Ic = nullptr;
@@ -80,7 +81,12 @@ struct Solver {
   int64_t launch_acc = 0;
 
   ~Solver();
-  void create(const tt_problem* p, const tt_solver_opts* o);
+  // Sets up the solver.  With size_only the device workspace it needs is
+  // stored there and nothing is allocated or copied; with ext (ext_bytes at
+  // least that size, 256-byte aligned) the caller's buffer is used instead of
+  // a hipMalloc and is borrowed until destruction.
+  void create(const tt_problem* p, const tt_solver_opts* o, void* ext = nullptr,
+              size_t ext_bytes = 0, size_t* size_only = nullptr);
   // One power step, blocking.
   void step(hipStream_t s, tt_step_info* info);
   // One power step as a task; drive it between enter() and leave().

@@ -243,7 +243,7 @@ void Solver::plan(Bump& b) {
 }
 
 Solver::~Solver() {
-  if (mem) (void)hipFree(mem);
+  if (mem && owns_mem) (void)hipFree(mem);
   if (slot.ev) (void)hipEventDestroy(slot.ev);
   if (hostmem) (void)hipHostFree(hostmem);
 }
@@ -262,7 +262,8 @@ void Solver::leave() {
   g_probe = nullptr;
 }
 
-void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
+void Solver::create(const tt_problem* p, const tt_solver_opts* o, void* ext, size_t ext_bytes,
+                    size_t* size_only) {
   TT_REQUIRE(p && o, "null problem or options");
   H = view(&p->H);
   SF = view(&p->SF);
@@ -430,7 +431,20 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o) {
   Bump dry;
   plan(dry);
   mem_bytes = dry.used + 4096;
-  TT_HIP(hipMalloc(&mem, mem_bytes));
+  if (size_only) {
+    *size_only = mem_bytes;
+    return;
+  }
+  if (ext) {
+    if (ext_bytes < mem_bytes)
+      throw CapacityError{"solver workspace smaller than tt_solver_workspace_size"};
+    TT_REQUIRE((reinterpret_cast<uintptr_t>(ext) & 255) == 0,
+               "solver workspace must be 256-byte aligned");
+    mem = ext;
+    owns_mem = false;
+  } else {
+    TT_HIP(hipMalloc(&mem, mem_bytes));
+  }
   TT_HIP(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming));
   TT_HIP(hipHostMalloc(&hostmem, (size_t)(6 * d + 32) * sizeof(double), hipHostMallocDefault));
   h_res = static_cast<double*>(hostmem);

@@ -26,7 +26,8 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_launches", "tt_solver_destroy", "tt_solver_set_probe",
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
-            "tt_local_apply", "ttnt_release", "tt_amen_mv"]
+            "tt_local_apply", "ttnt_release", "tt_amen_mv", "tt_solver_workspace_size",
+            "tt_solver_create_in"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -146,6 +147,11 @@ def lib():
                                      ctypes.c_size_t, v]
         L.tt_solver_create.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                        ctypes.POINTER(v)]
+        L.tt_solver_workspace_size.argtypes = [ctypes.POINTER(TTProblem),
+                                               ctypes.POINTER(TTSolverOpts),
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.tt_solver_create_in.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
+                                          v, ctypes.c_size_t, ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
         L.tt_power_step_batched.argtypes = [ctypes.POINTER(v), ctypes.c_int32,
                                             ctypes.POINTER(TTStepInfo), ctypes.POINTER(v),
@@ -424,7 +430,11 @@ class Solver:
                  max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  local_tol: float = 0.0, gmres_restart: int = 80, gmres_max_iter: int = 2000,
                  direct_max: int = 256, precision: int = 0, min_sweeps: int = 0,
-                 cap_eta: float = 0.0, stall: float = 0.0, krylov_path: int = 0):
+                 cap_eta: float = 0.0, stall: float = 0.0, krylov_path: int = 0,
+                 caller_workspace: bool = False):
+        """caller_workspace: the device workspace is a torch allocation made
+        here (tt_solver_workspace_size, tt_solver_create_in) instead of the
+        library's own hipMalloc."""
         self._hold = (H, SF, F_core0, cF, psi0)
         prob = TTProblem(H.desc(), SF.desc(), ctypes.c_void_p(F_core0.data_ptr()), cF.desc(),
                          psi0.desc(), float(k0))
@@ -433,7 +443,19 @@ class Solver:
                             int(gmres_max_iter), int(direct_max), int(precision),
                             int(min_sweeps), float(cap_eta), float(stall), int(krylov_path))
         h = ctypes.c_void_p()
-        _check(lib().tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)))
+        self.workspace = None
+        if caller_workspace:
+            nbytes = ctypes.c_size_t(0)
+            _check(lib().tt_solver_workspace_size(ctypes.byref(prob), ctypes.byref(opts),
+                                                  ctypes.byref(nbytes)))
+            self.workspace = _workspace(nbytes.value)
+            _check(lib().tt_solver_create_in(ctypes.byref(prob), ctypes.byref(opts),
+                                             ctypes.c_void_p(self.workspace.data_ptr()),
+                                             ctypes.c_size_t(self.workspace.numel() * 8),
+                                             ctypes.byref(h)))
+        else:
+            _check(lib().tt_solver_create(ctypes.byref(prob), ctypes.byref(opts),
+                                          ctypes.byref(h)))
         self.h = h
         self.d = H.d
         self.n = psi0.n.copy()

@@ -68,7 +68,7 @@ class KeffSolver:
                  kick: int = 4, max_sweeps: int = 20, rhs_mode: int = 0, rhs_rmax: int = 0,
                  direct_max: int = 256, gmres_restart: int = 80, ops=None, precision: int = 0,
                  min_sweeps: int = 0, cap_eta: float = 0.0, stall: float = 0.0,
-                 krylov_path: int = 0):
+                 krylov_path: int = 0, caller_workspace: bool = False):
         import torch
         self.wl = wl
         self.rmax = wl.rmax if rmax is None else rmax
@@ -89,7 +89,7 @@ class KeffSolver:
                                     rhs_rmax=rhs_rmax, direct_max=direct_max,
                                     gmres_restart=gmres_restart, precision=precision,
                                     min_sweeps=min_sweeps, cap_eta=cap_eta, stall=stall,
-                                    krylov_path=krylov_path)
+                                    krylov_path=krylov_path, caller_workspace=caller_workspace)
         self.history: List[StepRecord] = []
 
     @property

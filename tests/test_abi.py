@@ -130,6 +130,30 @@ def test_solver_rejects_bad_options():
     assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
 
 
+def test_solver_workspace_query_validates_before_reading_the_device():
+    lib = native.lib()
+    H, kh = _host_mat([2], [2], [1, 1])
+    SF, ks = _host_mat([2], [2], [1, 1])
+    cF, kc = _host_vec([2], [1, 1], [1, 1])
+    p0, kp = _host_vec([2], [1, 1], [1, 1])
+    prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, 1.0)
+    good = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64)
+    bad = native.TTSolverOpts(1e-8, 0, 4, 10, 0, 0, 0.0, 40, 100, 64)    # rmax = 0
+    nbytes = ctypes.c_size_t(0)
+    assert lib.tt_solver_workspace_size(None, ctypes.byref(good),
+                                        ctypes.byref(nbytes)) == native.TT_E_ARG
+    assert lib.tt_solver_workspace_size(ctypes.byref(prob), ctypes.byref(good),
+                                        None) == native.TT_E_ARG
+    assert lib.tt_solver_workspace_size(ctypes.byref(prob), ctypes.byref(bad),
+                                        ctypes.byref(nbytes)) == native.TT_E_ARG
+    h = ctypes.c_void_p()
+    assert lib.tt_solver_create_in(ctypes.byref(prob), ctypes.byref(good), None, 0,
+                                   ctypes.byref(h)) == native.TT_E_ARG
+    assert b"workspace" in lib.tt_last_error()
+    assert lib.tt_solver_create_in(ctypes.byref(prob), ctypes.byref(bad), ctypes.c_void_p(0x1000),
+                                   1 << 20, ctypes.byref(h)) == native.TT_E_ARG
+
+
 def test_batched_step_validates_arguments():
     lib = native.lib()
     infos = (native.TTStepInfo * 2)()

@@ -130,3 +130,42 @@ def test_power_steps_match_oracle_s8(cuda, maker):
         assert np.linalg.norm(_unit(got) - _unit(ref)) <= 1e-6, step
         psi, k = got, rec.k
     s.close()
+
+
+def test_caller_owned_workspace_steps_match_library_allocated(cuda):
+    # tt_solver_create_in runs the same kernels on a workspace the caller
+    # allocated, so every step is bit-identical to tt_solver_create's solver;
+    # a short or misaligned workspace is refused before anything is written.
+    import ctypes
+    import torch
+    from paper_2309_03347_amd import native
+    from paper_2309_03347_amd.solver import KeffSolver
+    wl = W.inner_box(l=3, G=2, N=4, seed=21, rmax=64, tol=1e-10)
+    a = KeffSolver(wl, rmax=64, max_sweeps=40)
+    b = KeffSolver(wl, rmax=64, max_sweeps=40, ops=a.ops, caller_workspace=True)
+    assert b.native.workspace is not None
+    for step in range(3):
+        print(f"caller workspace step {step}", flush=True)
+        ra, rb = a.step(), b.step()
+        assert ra.k == rb.k and ra.sweeps == rb.sweeps, (step, ra.k, rb.k)
+        for ca, cb in zip(a.psi_cores(), b.psi_cores()):
+            assert np.array_equal(ca, cb)
+    prob = native.TTProblem(b.H.desc(), b.SF.desc(), ctypes.c_void_p(b.F0_dev.data_ptr()),
+                            b.cF.desc(), b.psi0.desc(), 1.0)
+    opts = native.TTSolverOpts(1e-10, 64, 4, 40, 0, 0, 0.0, 80, 2000, 256)
+    nbytes = ctypes.c_size_t(0)
+    lib = native.lib()
+    assert lib.tt_solver_workspace_size(ctypes.byref(prob), ctypes.byref(opts),
+                                        ctypes.byref(nbytes)) == native.TT_OK
+    assert nbytes.value > 0
+    ws = torch.empty(nbytes.value // 8 + 64, dtype=torch.float64, device="cuda")
+    h = ctypes.c_void_p()
+    assert lib.tt_solver_create_in(ctypes.byref(prob), ctypes.byref(opts),
+                                   ctypes.c_void_p(ws.data_ptr()), nbytes.value - 8,
+                                   ctypes.byref(h)) == native.TT_E_CAPACITY
+    assert lib.tt_solver_create_in(ctypes.byref(prob), ctypes.byref(opts),
+                                   ctypes.c_void_p(ws.data_ptr() + 8), nbytes.value,
+                                   ctypes.byref(h)) == native.TT_E_ARG
+    assert b"aligned" in lib.tt_last_error()
+    a.close()
+    b.close()
