@@ -36,6 +36,7 @@ namespace ttnt {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;         // accelerator complex dies of the MI355X (dispatch round-robin)
 constexpr int kMaxRestart = 88;
 // LDS staging of the GEMM tiles: A chunks up to 128 rows; B chunks up to 64
 // columns, or a whole K x N right operand of up to kBFull doubles.
@@ -381,6 +382,7 @@ struct Ctx {
   int G, b, tid, lane;
   int m, ldv, nr1, nr0, nRR, a0, a1, nloc, K3;
   int sub, own0;  // with S > 1: the workgroup's index within its slice, first own element
+  int pslot;      // with S > 1: the workgroup's slot of partial products, sub r0 + slice
   int64_t e0;
   int TNf, Kp, Np;
   double* As;     // GEMM staging (kAsDoubles doubles of room)
@@ -871,10 +873,10 @@ __device__ void apply_slice_mfg(const SArgs& a, const Ctx& c, const E* Qfe, cons
 // 1 it copies the workgroup's own product).
 template <typename O>
 __device__ void mfg_reduce(const SArgs& a, const Ctx& c, O* out) {
-  const double* P = a.Py + (int64_t)c.a0 * a.S * c.nr1 + c.own0;
+  const double* P = a.Py + (int64_t)c.a0 * c.nr1 + c.own0;
   for (int e = c.tid; e < c.nloc; e += kThreads) {
     double acc = 0.0;
-    for (int q = 0; q < a.S; ++q) acc += ld_coherent(P + (int64_t)q * c.nr1 + e);
+    for (int q = 0; q < a.S; ++q) acc += ld_coherent(P + (int64_t)q * a.r0 * c.nr1 + e);
     out[e] = (O)acc;
   }
   __syncthreads();
@@ -905,11 +907,17 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
   c.nRR = a.n * a.RR;
   if (a.S > 1) {
     // S workgroups per slice, each owning a contiguous part of the slice's
-    // n r1 elements
+    // n r1 elements.  Workgroups are dispatched round-robin over the XCDs
+    // (b % kXcds); numbered XCD-major, the ones that take the same beta'
+    // range (same sub) share few XCDs, so their part of PhiR stays in those
+    // L2s.  (Only the speed depends on the dispatch order.)
+    const int x = c.b % kXcds, base = x * (c.G / kXcds) + min(x, c.G % kXcds);
+    const int L = base + c.b / kXcds;
     const int q = cdiv(c.nr1, a.S);
-    c.a0 = c.b / a.S;
+    c.sub = L / a.r0;
+    c.a0 = L - c.sub * a.r0;
     c.a1 = c.a0 + 1;
-    c.sub = c.b - c.a0 * a.S;
+    c.pslot = L;
     c.own0 = min(c.nr1, c.sub * q);
     c.nloc = min(c.nr1, c.own0 + q) - c.own0;
     c.e0 = (int64_t)c.a0 * c.nr1 + c.own0;
@@ -918,6 +926,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
     c.a1 = min(a.r0, c.a0 + a.spw);
     c.sub = 0;
     c.own0 = 0;
+    c.pslot = c.b;
     c.nloc = (c.a1 - c.a0) * c.nr1;
     c.e0 = (int64_t)c.a0 * c.nr1;
   }
@@ -1069,7 +1078,8 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
       apply_slice_mfma<double>(a, c, a.Q, a.phiR, a.x, 1.0, c.Yd);
     else if constexpr (MF == 2) {
       // the product (or this workgroup's partial of it) goes through Py
-      apply_slice_mfg<double, double>(a, c, a.Qf, a.phiR, a.x, 1.0, a.Py + (int64_t)b * c.nr1);
+      apply_slice_mfg<double, double>(a, c, a.Qf, a.phiR, a.x, 1.0,
+                                      a.Py + (int64_t)c.pslot * c.nr1);
       if (a.S > 1) grid_sync(a.bar, target, a.wait_limit);
       mfg_reduce<double>(a, c, c.Yd);
     }
@@ -1123,7 +1133,7 @@ __global__ __launch_bounds__(kThreads) void gmres_slices_kernel(SArgs a) {
         apply_slice_mfma<T>(a, c, Qw, phiRw, W, (T)(1.0 / nu), w);
       else if constexpr (MF == 2) {
         apply_slice_mfg<T, double>(a, c, reinterpret_cast<const T*>(a.Qfw), phiRw, W,
-                                   (T)(1.0 / nu), a.Py + (int64_t)b * c.nr1);
+                                   (T)(1.0 / nu), a.Py + (int64_t)c.pslot * c.nr1);
         if (a.S > 1) grid_sync(a.bar, target, a.wait_limit);
         mfg_reduce<T>(a, c, w);
       }
