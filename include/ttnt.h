@@ -325,6 +325,27 @@ tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts
  */
 tt_status tt_solver_workspace_size(const tt_problem* problem, const tt_solver_opts* opts,
                                    size_t* bytes);
+/*
+ * tt_power_step_async - one power step (eq. TT_k_eff_fixed_points) at psi's
+ * current ranks with no host synchronization, so that a stream capture can
+ * record it as a graph and replays repeat it: `sweeps` (0: opts.max_sweeps)
+ * one-site alternating sweeps for H psi+ = (S + F/k) psi (each core's Galerkin system
+ * solved as in tt_power_step, the solved core split by QR with R moved into
+ * the next core, no truncation or enrichment), then psi+ right-orthonormal in
+ * cores 1..d-1, k+ = k <cF, psi+> / <cF, psi> and the unit-norm scaling, all
+ * on the device.  device_info (device memory, written by a kernel at the end
+ * of the step) receives k, k_prev, dk, the largest local residual seen
+ * before a solve in the last sweep, sweeps, max_rank, the GMRES iterations,
+ * and status: TT_OK, TT_E_NOCONV (that residual above tol), TT_E_NUMERIC (a
+ * non-finite k or residual) or TT_E_HIP (a persistent solve gave up at a
+ * grid barrier).  The ranks never change, so run tt_power_step until they
+ * settle first.  Requirements: rhs_mode 0, the kernel probe off, and every
+ * local system on a path without host readback (dense, mode-diagonal
+ * blocks, or the persistent GMRES kernel); otherwise TT_E_ARG (the stream
+ * may then hold part of the step's launches).  Returns after enqueueing.
+ */
+tt_status tt_power_step_async(tt_solver* s, int32_t sweeps, tt_step_info* device_info,
+                              tt_stream stream);
 tt_status tt_solver_create_in(const tt_problem* problem, const tt_solver_opts* opts,
                               void* workspace, size_t workspace_bytes, tt_solver** out);
 tt_status tt_power_step(tt_solver* s, tt_step_info* info, tt_stream stream);

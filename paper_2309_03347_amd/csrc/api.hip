@@ -374,6 +374,15 @@ tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts
   return solver_create(problem, opts, nullptr, 0, out);
 }
 
+tt_status tt_power_step_async(tt_solver* s, int32_t sweeps, tt_step_info* device_info,
+                              tt_stream stream) {
+  return guard([&] {
+    TT_REQUIRE(s && device_info, "NULL argument");
+    TT_REQUIRE(sweeps >= 0, "sweeps must be >= 0");
+    s->impl.step_async((hipStream_t)stream, sweeps, device_info);
+  });
+}
+
 tt_status tt_solver_workspace_size(const tt_problem* problem, const tt_solver_opts* opts,
                                    size_t* bytes) {
   return guard([&] {

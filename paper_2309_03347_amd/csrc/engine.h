@@ -124,6 +124,11 @@ struct LocalSolveOpts {
   bool lowp = false;       // multi-launch GMRES: operator products on the BF16 matrix cores
                            // inside each restart cycle, FP64 residual at every restart
   double inner_tol_lp = 1e-2;  // lowp: a cycle ends once its residual fell by this factor
+  // Set for solves inside a step that must not wait for the device: a
+  // persistent GMRES solve copies its 5-double info there (device to device)
+  // instead of reading it back, and every path that needs the host between
+  // launches (the multi-launch GMRES) is refused.
+  double* dev_info = nullptr;
 };
 struct LocalSolveResult {
   int iterations = 0;

@@ -435,7 +435,9 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
     const bool probed = krylov_solve(s, sh, op.phiL, op.Ap, op.phiR, f, x, m, o.max_iter, o.tol,
                                      o.eta, kws, kw, scal, grid, mixed, o.inner_tol);
     const int slot = probed ? g_probe->last_slot() : -1;
-    if (defer_info && !final_res) {
+    if (o.dev_info) {
+      copy(s, scal, o.dev_info, 5);
+    } else if (defer_info && !final_res) {
       TT_HIP(hipMemcpyAsync(defer_info, scal, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
       res.deferred = true;
       res.probe_slot = slot;
@@ -449,6 +451,9 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
       krylov_probe_amend(op, o.restart, res.iterations, slot, mixed);
     }
   } else {
+    if (o.dev_info)
+      throw ArgError{"asynchronous step: a local system outside the persistent GMRES kernel "
+                     "(multi-launch GMRES needs the host between launches)"};
     res.method = method;
     const int m = std::max(2, std::min(o.restart, 88));
     double* V = ws.d((int64_t)(m + 1) * N);

@@ -65,6 +65,7 @@ struct Solver {
   static constexpr size_t kSplitK = (size_t)1 << 21;   // split-K partials (doubles)
   double* splitk = nullptr;
   double *scal = nullptr, *resarr = nullptr;
+  double* kry_dev = nullptr;   // 5 per core: persistent GMRES info of the asynchronous step
   int* irank = nullptr;
 
   // host synchronization of the step task: its event and pinned readbacks
@@ -91,6 +92,11 @@ struct Solver {
   void step(hipStream_t s, tt_step_info* info);
   // One power step as a task; drive it between enter() and leave().
   Co step_co(hipStream_t s, tt_step_info* info);
+  // One power step at the current ranks with no host synchronization (so a
+  // stream capture can record it): max_sweeps one-site alternating sweeps
+  // (QR splits, no truncation or enrichment), the k update and the
+  // normalization; the step information goes to device memory.
+  void step_async(hipStream_t s, int sweeps, tt_step_info* device_info);
   // Bind / release this solver's thread-local context (split-K scratch,
   // kernel probe, launch counter) around each resumption of its task.
   void enter();
@@ -103,6 +109,7 @@ struct Solver {
   Co sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
                    const std::vector<double*>& ApOp, const std::vector<ModeForm>& fOp,
                    StepStats& st);
+  void sweep_core_async(hipStream_t s, int k, const LocalSolveOpts& lo);
 };
 
 

@@ -239,6 +239,7 @@ void Solver::plan(Bump& b) {
   splitk = b.d(kSplitK);
   scal = b.d(64);
   resarr = b.d(dd + 8);
+  kry_dev = b.d(5 * (int64_t)dd + 8);
   irank = b.i(16);
 }
 
@@ -659,6 +660,140 @@ Co Solver::sweep_core_co(hipStream_t s, int k, const TTv& V, const TTm& Aop,
              LZH[k + 1], T1, T2, formH[k]);
   iface_left(s, LZA[k], Z.core(k), zk, kz, ApOp[k], Rop[k], nk, nk, Rop[k + 1], V.core(k), vk,
              vk1, LZA[k + 1], T1, T2, fOp[k]);
+}
+
+namespace {
+
+// tt_step_info of the asynchronous step, formed on the device: k and k_prev
+// from the k update, the largest local residual seen before a solve in the
+// last sweep, the GMRES iterations summed from the per-core infos, and the
+// status (TT_E_HIP when a persistent solve gave up at a grid barrier,
+// TT_E_NUMERIC on a non-finite k or residual, TT_E_NOCONV when the last
+// sweep's largest residual is above tol).
+__global__ void step_info_kernel(const double* kinfo, const double* res, const double* kry, int d,
+                                 double tol, int sweeps, int max_rank, tt_step_info* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mr = 0.0;
+  bool finite = true;
+  long long iters = 0;
+  bool gave_up = false;
+  for (int k = 0; k < d; ++k) {
+    const double r = res[k];
+    if (!(r == r) || isinf(r)) finite = false;
+    mr = fmax(mr, r);
+    iters += (long long)kry[5 * k];
+    if (kry[5 * k + 4] != 0.0) gave_up = true;
+  }
+  tt_step_info v;
+  v.k = kinfo[0];
+  v.k_prev = kinfo[1];
+  v.dk = fabs(kinfo[0] - kinfo[1]);
+  v.max_local_res = mr;
+  v.trunc_err = 0.0;
+  v.sweeps = sweeps;
+  v.max_rank = max_rank;
+  v.local_iters = (int32_t)iters;
+  if (!(v.k == v.k) || isinf(v.k)) finite = false;
+  v.status = gave_up ? TT_E_HIP : (!finite ? TT_E_NUMERIC : (mr < tol ? TT_OK : TT_E_NOCONV));
+  *out = v;
+}
+
+}  // namespace
+
+void Solver::sweep_core_async(hipStream_t s, int k, const LocalSolveOpts& lo) {
+  const int rk = X.r[k], rk1 = X.r[k + 1], nk = n[k];
+  const int vk = psi.r[k], vk1 = psi.r[k + 1];
+  LocalOp xh{LXH[k], rk, RH[k], rk, ApH[k], H.core(k), nk, nk, RH[k + 1], RXH[k + 1], rk1, rk1,
+             (bool)Hdiag[k]};
+  LocalOp xa{LXA[k], rk, Rop[k], vk, ApA[k], Ak.core(k), nk, nk, Rop[k + 1], RXA[k + 1], rk1, vk1};
+  xh.form = formH[k];
+  xa.form = formSF[k];
+  const int64_t N = (int64_t)rk * nk * rk1;
+  local_apply(s, xa, psi.core(k), fvec, 1.0, 0.0, T1, T2);
+  local_apply(s, xh, X.core(k), yvec, 1.0, 0.0, T1, T2);
+  rel_res(s, yvec, fvec, N, resarr + k);
+  copy(s, X.core(k), xloc, N);
+  Bump lw;
+  lw.base = (char*)lsw;
+  lw.cap = ls_cap;
+  LocalSolveOpts o = lo;
+  o.dev_info = kry_dev + 5 * k;
+  local_solve(s, xh, fvec, xloc, o, lw, false, nullptr);
+  if (k == d - 1) {
+    copy(s, xloc, X.core(k), N);
+    return;
+  }
+  // one-site split: QR of the solved core, (r_k n_k) x r_{k+1}; R moves into
+  // core k + 1
+  const int rows = rk * nk, q = std::min(rows, rk1);
+  qr(s, xloc, rows, rk1, rk1, X.core(k), q, Rb, rk1, tau);
+  const int n2 = n[k + 1] * X.r[k + 2];
+  gemm(s, false, false, q, n2, rk1, 1.0, Rb, rk1, 0, X.core(k + 1), n2, 0, 0.0, tmp, n2, 0);
+  copy(s, tmp, X.core(k + 1), (int64_t)q * n2);
+  X.r[k + 1] = q;
+  iface_left(s, LXH[k], X.core(k), rk, q, ApH[k], RH[k], nk, nk, RH[k + 1], X.core(k), rk, q,
+             LXH[k + 1], T1, T2, formH[k]);
+  iface_left(s, LXA[k], X.core(k), rk, q, ApA[k], Rop[k], nk, nk, Rop[k + 1], psi.core(k), vk,
+             vk1, LXA[k + 1], T1, T2, formSF[k]);
+}
+
+void Solver::step_async(hipStream_t s, int sweeps, tt_step_info* device_info) {
+  TT_REQUIRE(rhs_mode == 0 && !product_only,
+             "the asynchronous step needs the projected right-hand side of a k solve");
+  TT_REQUIRE(!probe.active, "the asynchronous step runs without the kernel probe");
+  if (sweeps <= 0) sweeps = max_sweeps;
+  enter();
+  try {
+    g_launches = 0;
+    // A(k) core 0 = SF_0 + F_0 / k (k read on the device)
+    copy(s, F0, A0, SF.size(0));
+    axpby_div(s, SF.size(0), 1.0, SF.core(0), 1.0, scal + KVAL, A0);
+    permute_op(s, A0, SF.R[0], n[0], n[0], SF.R[1], ApA[0]);
+    if (formSF[0].kind == 2) rank1_rows(s, A0, SF.R[0], n[0], SF.R[1], sf_j0[0], ArpSF[0]);
+    fill(s, kry_dev, 5 * (int64_t)d, 0.0);
+    LocalSolveOpts lo = lso;
+    lo.eta = 0.0;
+    Bump w;
+    w.base = rw;
+    w.cap = rw_cap;
+    X.r = psi.r;
+    for (int k = 0; k < d; ++k) copy(s, psi.core(k), X.core(k), psi.size(k));
+    for (int sw = 0; sw < sweeps; ++sw) {
+      // right-orthonormal cores 1..d-1, then the right interfaces
+      w.used = 0;
+      orth_right(s, X, w);
+      for (int k = d - 1; k >= 1; --k) {
+        iface_right(s, RXH[k + 1], X.core(k), X.r[k], X.r[k + 1], ApH[k], RH[k], n[k], n[k],
+                    RH[k + 1], X.core(k), X.r[k], X.r[k + 1], RXH[k], T1, T2, formH[k]);
+        iface_right(s, RXA[k + 1], X.core(k), X.r[k], X.r[k + 1], ApA[k], Rop[k], n[k], n[k],
+                    Rop[k + 1], psi.core(k), psi.r[k], psi.r[k + 1], RXA[k], T1, T2, formSF[k]);
+      }
+      for (int k = 0; k < d; ++k) sweep_core_async(s, k, lo);
+    }
+    // psi <- X, right-orthonormal in cores 1..d-1 as every step leaves it (so
+    // the norm is core 0's), then the k update and the unit-norm scaling
+    psi.r = X.r;
+    for (int k = 0; k < d; ++k) copy(s, X.core(k), psi.core(k), X.size(k));
+    w.used = 0;
+    orth_right(s, psi, w);
+    w.used = 0;
+    dot_tt(s, cF, psi, scal + NUM, w);
+    k_update(s, scal + KVAL, scal + NUM, scal + DEN, scal + KINFO);
+    sumsq(s, psi.core(0), psi.size(0), scal + NRM2);
+    scale_inv_sqrt(s, psi.core(0), psi.size(0), scal + NRM2);
+    scale_ratio(s, scal + NUM, scal + NRM2, scal + DEN);
+    int mr = 0;
+    for (int v : psi.r) mr = std::max(mr, v);
+    ++g_launches;
+    step_info_kernel<<<1, 64, 0, s>>>(scal + KINFO, resarr, kry_dev, d, tol, sweeps, mr,
+                                      device_info);
+    TT_HIP(hipGetLastError());
+    last_launches = g_launches;
+  } catch (...) {
+    leave();
+    throw;
+  }
+  leave();
 }
 
 double Solver::step_cost() const {

@@ -27,7 +27,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
             "tt_local_apply", "ttnt_release", "tt_amen_mv", "tt_solver_workspace_size",
-            "tt_solver_create_in"]
+            "tt_solver_create_in", "tt_power_step_async"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -153,6 +153,7 @@ def lib():
         L.tt_solver_create_in.argtypes = [ctypes.POINTER(TTProblem), ctypes.POINTER(TTSolverOpts),
                                           v, ctypes.c_size_t, ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
+        L.tt_power_step_async.argtypes = [v, ctypes.c_int32, v, v]
         L.tt_power_step_batched.argtypes = [ctypes.POINTER(v), ctypes.c_int32,
                                             ctypes.POINTER(TTStepInfo), ctypes.POINTER(v),
                                             ctypes.c_int32]
@@ -170,6 +171,18 @@ def lib():
                 getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
+
+
+def step_info_buffer():
+    """A device buffer for tt_power_step_async's tt_step_info."""
+    torch = _torch()
+    return torch.zeros(ctypes.sizeof(TTStepInfo), dtype=torch.uint8, device="cuda")
+
+
+def read_step_info(buf) -> dict:
+    """Decode a device tt_step_info (copies it to the host; synchronizes)."""
+    raw = bytes(buf.cpu().numpy().tobytes())
+    return _info_dict(TTStepInfo.from_buffer_copy(raw))
 
 
 def _check(status: int, allow=()):
@@ -465,6 +478,13 @@ class Solver:
         st = lib().tt_power_step(self.h, ctypes.byref(info), _stream())
         _check(st, allow=(TT_E_NOCONV,))
         return _info_dict(info)
+
+    def step_async(self, device_info, sweeps: int = 0) -> None:
+        """Enqueue one fixed-rank step with no host synchronization (capturable);
+        device_info: a CUDA uint8 tensor of ctypes.sizeof(TTStepInfo) bytes;
+        sweeps 0: the solver's max_sweeps."""
+        _check(lib().tt_power_step_async(self.h, int(sweeps),
+                                         ctypes.c_void_p(device_info.data_ptr()), _stream()))
 
     def ranks(self) -> np.ndarray:
         r = np.zeros(self.d + 1, dtype=np.int32)

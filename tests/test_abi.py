@@ -154,6 +154,15 @@ def test_solver_workspace_query_validates_before_reading_the_device():
                                    1 << 20, ctypes.byref(h)) == native.TT_E_ARG
 
 
+def test_async_step_validates_arguments():
+    lib = native.lib()
+    assert lib.tt_power_step_async(None, 0, ctypes.c_void_p(0x1000), None) == native.TT_E_ARG
+    assert lib.tt_power_step_async(ctypes.c_void_p(0x1000), 0, None, None) == native.TT_E_ARG
+    assert b"NULL" in lib.tt_last_error()
+    assert lib.tt_power_step_async(ctypes.c_void_p(0x1000), -1, ctypes.c_void_p(0x1000),
+                                   None) == native.TT_E_ARG
+
+
 def test_batched_step_validates_arguments():
     lib = native.lib()
     infos = (native.TTStepInfo * 2)()
