@@ -93,6 +93,11 @@ def _parse():
     p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision comparison run")
+    p.add_argument("--graph-steps", type=int, default=5,
+                   help="replays of the captured fixed-rank step (tt_power_step_async) after "
+                        "the timed steps (0: skip)")
+    p.add_argument("--graph-sweeps", type=int, default=2,
+                   help="alternating sweeps of the captured fixed-rank step")
     p.add_argument("--ttk-steps", type=int, default=20,
                    help="step limit of the time-to-k run (0 skips it)")
     p.add_argument("--probe-steps", type=int, default=5,
@@ -212,6 +217,82 @@ def _build_ops(w):
     return operators.build(w)
 
 
+def _batch_graph_leg(solvers, args):
+    """Every instance's fixed-rank step (tt_power_step_async) captured as a
+    graph of its own at its current ranks; one batched step replays all the
+    graphs in order on one stream (no host synchronization inside)."""
+    import torch
+    from paper_2309_03347_amd import native
+    graphs, bufs, failed = [], [], []
+    torch.cuda.synchronize()
+    for i, sv in enumerate(solvers):
+        buf = native.step_info_buffer()
+        g = torch.cuda.CUDAGraph()
+        try:
+            with torch.cuda.graph(g):
+                sv.native.step_async(buf, sweeps=args.graph_sweeps)
+        except Exception as e:
+            failed.append((i, f"{type(e).__name__}: {e}"[:160]))
+            continue
+        graphs.append(g)
+        bufs.append(buf)
+    torch.cuda.synchronize()
+    print(f"{len(graphs)} instance graphs captured", file=sys.stderr, flush=True)
+    if not graphs:
+        return dict(error="no instance step could be captured", failed=failed[:4])
+    for g in graphs:           # one untimed round
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(args.graph_steps):
+        for g in graphs:
+            g.replay()
+        print(f"graph batched step {r} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    infos = [native.read_step_info(b) for b in bufs]
+    return dict(value=len(graphs) * args.graph_steps / dt, unit="instance-steps/s",
+                ms_per_batched_step=1e3 * dt / args.graph_steps, instances=len(graphs),
+                sweeps=args.graph_sweeps, not_captured=len(failed), failed=failed[:4],
+                status_counts={str(st): sum(1 for x in infos if x["status"] == st)
+                               for st in sorted(set(x["status"] for x in infos))},
+                note="per-instance graphs of the fixed-rank step at the ranks the adaptive "
+                     "steps reached, replayed in order on one stream")
+
+
+def _graph_leg(s, args):
+    """The fixed-rank power step with no host synchronization
+    (tt_power_step_async) captured once as a graph at the ranks the timed
+    steps reached, then replayed: steps/s of the replays and the last
+    replay's step information."""
+    import torch
+    from paper_2309_03347_amd import native
+    buf = native.step_info_buffer()
+    k0 = s.history[-1].k
+    try:
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            s.native.step_async(buf, sweeps=args.graph_sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            g.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    except Exception as e:           # reported, not fatal for the bench line
+        return dict(error=f"{type(e).__name__}: {e}")
+    info = native.read_step_info(buf)
+    return dict(value=args.graph_steps / dt, unit="steps/s",
+                ms_per_step=1e3 * dt / args.graph_steps, replays=args.graph_steps,
+                sweeps=args.graph_sweeps, ranks="fixed at the adaptive steps' last ranks",
+                k=info["k"], k_rel_diff_vs_adaptive_start=abs(info["k"] - k0) / abs(k0),
+                max_local_res=info["max_local_res"], status=info["status"],
+                note="one-site alternating sweeps with QR splits at fixed ranks (no truncation "
+                     "or enrichment), k update and normalization on the device; one graph "
+                     "launch per step")
+
+
 def _roofline(probe, workload):
     """Roofline of the dominant kernel class (by total device time) of a probe."""
     name, st = max(probe.items(), key=lambda kv: kv[1]["total_ms"])
@@ -290,6 +371,7 @@ def _bench_batch(args):
         print(f"timed batched step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    graph = _batch_graph_leg(solvers, args) if args.graph_steps > 0 else None
     # kernel probe over one more batched step: every solver's launches of the
     # timed classes bracketed by HIP events on its own stream
     roofline = None
@@ -341,6 +423,7 @@ def _bench_batch(args):
                    "instances": len(solvers), "streams": args.streams,
                    "setup_seconds": setup},
         "max_rank": int(max(max(s.native.ranks()) for s in solvers)),
+        "graph_step": graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -478,6 +561,9 @@ def main():
     if not args.no_cpu_baseline:
         cpu = _cpu_baseline(wl, args.cpu_seconds)
 
+    graph = None
+    if args.graph_steps > 0:
+        graph = _graph_leg(s, args)
     largest = None
     if args.largest_steps > 0 and args.workload != "checkerboard_n1024_G16_S16":
         largest = _largest(args)
@@ -508,6 +594,7 @@ def main():
         "time_to_k": ttk,
         "time_to_k_small": ttk_small,
         "mixed": mixed,
+        "graph_step": graph,
         "largest_config": largest,
     }
     if probe is not None:
