@@ -496,12 +496,14 @@ def main():
     wl = builder(W)
     rmax = args.rmax or wl.rmax
     s = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode)
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         s.step()
+        print(f"{args.workload}: warmup step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         s.step()
+        print(f"{args.workload}: timed step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps / dt
