@@ -41,8 +41,8 @@ MEASURED_TRAFFIC = {
     # 2.0) plus WRITE_SIZE (scaled by 1.0) over the timed steps of a profiled
     # bench run, valid while the kernel sources hash to the prefixes below
     ("krylov", "checkerboard_n128_G8_S8"): dict(
-        bytes_per_launch=175.1e6,
-        sources={"paper_2309_03347_amd/csrc/krylov.hip": "7e598c95c04d2eac",
+        bytes_per_launch=1.692e9,
+        sources={"paper_2309_03347_amd/csrc/krylov.hip": "98e4ecaad4f2c90e",
                  "paper_2309_03347_amd/csrc/gemm_tile.h": "8641b1e5a94501dd"}),
 }
 
