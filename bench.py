@@ -219,12 +219,17 @@ def _build_ops(w):
 
 def _batch_graph_leg(solvers, args):
     """Every instance's fixed-rank step (tt_power_step_async) captured as a
-    graph of its own at its current ranks; one batched step replays all the
-    graphs in order on one stream (no host synchronization inside)."""
+    graph of its own at its current ranks, its persistent GMRES grids capped
+    at 256 / streams workgroups; one batched step replays the graphs
+    round-robin on the streams, so that up to `streams` instances run at
+    once (no host synchronization inside a step)."""
     import torch
     from paper_2309_03347_amd import native
     graphs, bufs, failed = [], [], []
+    nst = max(1, args.streams)
+    streams = [torch.cuda.Stream() for _ in range(nst)]
     torch.cuda.synchronize()
+    native.set_grid_cap(256 // nst)
     for i, sv in enumerate(solvers):
         buf = native.step_info_buffer()
         g = torch.cuda.CUDAGraph()
@@ -236,17 +241,20 @@ def _batch_graph_leg(solvers, args):
             continue
         graphs.append(g)
         bufs.append(buf)
+    native.set_grid_cap(0)
     torch.cuda.synchronize()
     print(f"{len(graphs)} instance graphs captured", file=sys.stderr, flush=True)
     if not graphs:
         return dict(error="no instance step could be captured", failed=failed[:4])
-    for g in graphs:           # one untimed round
-        g.replay()
+    def batched_step():
+        for i, g in enumerate(graphs):
+            with torch.cuda.stream(streams[i % nst]):
+                g.replay()
+    batched_step()             # one untimed round
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(args.graph_steps):
-        for g in graphs:
-            g.replay()
+        batched_step()
         print(f"graph batched step {r} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -256,8 +264,9 @@ def _batch_graph_leg(solvers, args):
                 sweeps=args.graph_sweeps, not_captured=len(failed), failed=failed[:4],
                 status_counts={str(st): sum(1 for x in infos if x["status"] == st)
                                for st in sorted(set(x["status"] for x in infos))},
+                streams=nst, grid_cap=256 // nst,
                 note="per-instance graphs of the fixed-rank step at the ranks the adaptive "
-                     "steps reached, replayed in order on one stream")
+                     "steps reached, replayed round-robin on the streams")
 
 
 def _graph_leg(s, args):

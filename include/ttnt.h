@@ -222,6 +222,15 @@ tt_status tt_local_solve_noalloc(const tt_local* sys, double* x, const tt_solve_
  * give up (used to test the error path).  TT_E_ARG for NaN.
  */
 tt_status ttnt_set_grid_wait_limit(double seconds);
+/*
+ * ttnt_set_grid_cap - caps the workgroups of the persistent GMRES launches
+ * that the calling host thread enqueues from now on (0 restores the default,
+ * 256), for callers that run several solves at once on different streams:
+ * with every grid within (compute units / concurrent streams) all of them can
+ * be resident together, as the grid barriers require.  The cap is recorded in
+ * launches captured into graphs.  TT_E_ARG for a negative cap.
+ */
+tt_status ttnt_set_grid_cap(int32_t cap);
 
 /*
  * ttnt_release - waits for the device, then frees the HIP event and pinned

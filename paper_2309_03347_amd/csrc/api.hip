@@ -374,6 +374,13 @@ tt_status tt_solver_create(const tt_problem* problem, const tt_solver_opts* opts
   return solver_create(problem, opts, nullptr, 0, out);
 }
 
+tt_status ttnt_set_grid_cap(int32_t cap) {
+  return guard([&] {
+    TT_REQUIRE(cap >= 0, "cap must be >= 0");
+    krylov_set_thread_cap(cap);
+  });
+}
+
 tt_status tt_power_step_async(tt_solver* s, int32_t sweeps, tt_step_info* device_info,
                               tt_stream stream) {
   return guard([&] {

@@ -27,7 +27,7 @@ EXPORTED = ["ttnt_version", "tt_last_error", "tt_matvec", "tt_round_workspace", 
             "tt_solver_probe_stats", "tt_power_step_batched", "tt_local_solve_noalloc",
             "ttnt_set_grid_wait_limit", "tt_orth_right", "tt_local_apply_workspace",
             "tt_local_apply", "ttnt_release", "tt_amen_mv", "tt_solver_workspace_size",
-            "tt_solver_create_in", "tt_power_step_async"]
+            "tt_solver_create_in", "tt_power_step_async", "ttnt_set_grid_cap"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -154,6 +154,7 @@ def lib():
                                           v, ctypes.c_size_t, ctypes.POINTER(v)]
         L.tt_power_step.argtypes = [v, ctypes.POINTER(TTStepInfo), v]
         L.tt_power_step_async.argtypes = [v, ctypes.c_int32, v, v]
+        L.ttnt_set_grid_cap.argtypes = [ctypes.c_int32]
         L.tt_power_step_batched.argtypes = [ctypes.POINTER(v), ctypes.c_int32,
                                             ctypes.POINTER(TTStepInfo), ctypes.POINTER(v),
                                             ctypes.c_int32]
@@ -171,6 +172,11 @@ def lib():
                 getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
+
+
+def set_grid_cap(cap: int) -> None:
+    """Cap the persistent GMRES grids this thread launches (0: default)."""
+    _check(lib().ttnt_set_grid_cap(int(cap)))
 
 
 def step_info_buffer():

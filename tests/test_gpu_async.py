@@ -94,3 +94,49 @@ def test_captured_async_step_replays_match_eager_steps(cuda):
             assert np.array_equal(ca, cb), r
     a.close()
     b.close()
+
+
+def test_capped_graphs_replay_concurrently_on_two_streams(cuda):
+    # two instances' fixed-rank steps captured with their persistent grids
+    # capped at 128 workgroups and replayed at once on two streams equal the
+    # same steps enqueued eagerly one after the other
+    import torch
+    from paper_2309_03347_amd import native
+    wls = [W.inner_box(l=3, G=2, N=4, seed=21, rmax=64, tol=1e-10),
+           W.homogeneous(l=3, N=2, seed=3, tol=1e-10)]
+    eager = [_settled(w) for w in wls]
+    graphed = [_settled(w) for w in wls]
+    bufs_e = [native.step_info_buffer() for _ in wls]
+    bufs_g = [native.step_info_buffer() for _ in wls]
+    graphs = []
+    torch.cuda.synchronize()
+    native.set_grid_cap(128)
+    try:
+        for s, b in zip(graphed, bufs_g):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                s.native.step_async(b, sweeps=3)
+            graphs.append(g)
+    finally:
+        native.set_grid_cap(0)
+    streams = [torch.cuda.Stream() for _ in wls]
+    for r in range(2):
+        print(f"concurrent replay {r}", flush=True)
+        # the same cap, so both take the same work split (and sum order)
+        native.set_grid_cap(128)
+        try:
+            for s, b in zip(eager, bufs_e):
+                s.native.step_async(b, sweeps=3)
+        finally:
+            native.set_grid_cap(0)
+        torch.cuda.synchronize()
+        for g, st in zip(graphs, streams):
+            with torch.cuda.stream(st):
+                g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(wls)):
+            assert native.read_step_info(bufs_e[i]) == native.read_step_info(bufs_g[i]), (r, i)
+            for ca, cb in zip(eager[i].psi_cores(), graphed[i].psi_cores()):
+                assert np.array_equal(ca, cb), (r, i)
+    for s in eager + graphed:
+        s.close()
