@@ -609,8 +609,9 @@ __device__ void apply_slice_mfma(const SArgs& a, const Ctx& c, const E* Qe, cons
 // of the rows c and takes them in equal passes of at most kS3Rows, its lanes
 // along k (16-byte loads when the rows are aligned): every load of PhiR uses
 // whole cache lines, each T value read from LDS serves the pass's rows, and
-// one pass over k keeps that many loads per lane in flight.  The 64 lanes'
-// sums are added by butterflies at the end of the pass.
+// the loads of the next k position are in flight while the current ones are
+// multiplied.  The 64 lanes' sums are added by butterflies at the end of the
+// pass.
 constexpr int kS3Rows = 8;
 
 template <typename E, typename O>
@@ -641,20 +642,39 @@ __device__ void stage3_rows(const SArgs& a, const Ctx& c, const E* phiRe, int K,
         const VW* tb = reinterpret_cast<const VW*>(t1);
         const VW* p0 = reinterpret_cast<const VW*>(phiRe + (int64_t)c0 * K3);
         const int64_t rs = K3 / W;     // row stride in loads
-#pragma unroll (W == 2 ? 2 : 1)
-        for (int k = l; k < KW; k += 64) {
-          VW pv[CR];
+        // every lane takes the same T = ceil(KW / 64) positions (the last
+        // clamped to the row and counted with zero weight), so the loads are
+        // unconditional and double-buffered: the next position's CR loads are
+        // in flight while the current ones are multiplied
+        const int T = (KW + 63) / 64;
+        auto ldp = [&](VW* buf, int t) {
+          const int kk = min(l + 64 * t, KW - 1);
 #pragma unroll
-          for (int r = 0; r < CR; ++r) pv[r] = p0[(int64_t)min(r, nr - 1) * rs + k];
-          const VW x0 = ta[k], x1 = tb[k];
+          for (int r = 0; r < CR; ++r) buf[r] = p0[(int64_t)min(r, nr - 1) * rs + kk];
+        };
+        auto mac = [&](const VW* buf, int t) {
+          const int kk = l + 64 * t;
+          const bool ok = kk < KW;
+          const VW zero = VW{};
+          const VW x0 = ok ? ta[kk] : zero, x1 = ok ? tb[kk] : zero;
 #pragma unroll
           for (int r = 0; r < CR; ++r)
 #pragma unroll
             for (int h = 0; h < W; ++h) {
-              acc[r][0] = fma((double)x0[h], (double)pv[r][h], acc[r][0]);
-              acc[r][1] = fma((double)x1[h], (double)pv[r][h], acc[r][1]);
+              acc[r][0] = fma((double)x0[h], (double)buf[r][h], acc[r][0]);
+              acc[r][1] = fma((double)x1[h], (double)buf[r][h], acc[r][1]);
             }
+        };
+        VW pa[CR], pb[CR];
+        ldp(pa, 0);
+        int t = 0;
+        for (; t + 1 < T; t += 2) {
+          ldp(pb, t + 1);
+          mac(pa, t);
+          if (t + 2 < T) ldp(pa, t + 2);
+          mac(pb, t + 1);
         }
+        if (t < T) mac(pa, t);
       } else {
         for (int k = l; k < K; k += 64) {
           const E x0 = t0[k], x1 = t1[k];
