@@ -152,13 +152,16 @@ def test_persistent_gmres_bench_shapes(cuda, ra, RL, n, RR, rc, restart):
     assert np.linalg.norm(out[(2, 0)] - out[(4, 0)]) <= 1e-9 * np.linalg.norm(out[(4, 0)])
 
 
-def test_grid_barrier_wait_gives_up_with_an_error(cuda):
+@pytest.mark.parametrize("ra,RL,n,RR,rc", [
+    (36, 6, 2, 8, 36),       # 36 workgroups
+    (64, 24, 2, 72, 64),     # 256 workgroups (four per slice)
+])
+def test_grid_barrier_wait_gives_up_with_an_error(cuda, ra, RL, n, RR, rc):
     # A limit <= 0 makes every workgroup that has to wait give up at once: the
     # solve must end (every workgroup exits) and report TT_E_HIP.  The wait is
     # forced from the host; no workgroup is ever left unable to proceed.
     from paper_2309_03347_amd import native
     rng = np.random.default_rng(11)
-    ra, RL, n, RR, rc = 36, 6, 2, 8, 36
     phiL, A, phiR, f = _system(rng, ra, RL, n, RR, rc)
     shape = (ra, n, rc)
     args = (_t(phiL), _t(A), _t(phiR), _t(f.reshape(shape)), _t(np.zeros(shape)))
