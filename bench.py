@@ -93,6 +93,8 @@ def _parse():
     p.add_argument("--instances", type=int, default=256, help="instances of the batched workload")
     p.add_argument("--no-mixed", action="store_true",
                    help="skip the mixed-precision comparison run")
+    p.add_argument("--mixed-precision", type=int, default=2, choices=(2, 3),
+                   help="precision of the mixed run: 2 BF16, 3 block-scaled FP16 products")
     p.add_argument("--graph-steps", type=int, default=5,
                    help="replays of the captured fixed-rank step (tt_power_step_async) after "
                         "the timed steps (0: skip)")
@@ -213,8 +215,15 @@ def _time_to_k(wl, rmax, rhs_mode, max_steps, rel=1e-5, precision=0):
 
 
 def _build_ops(w):
+    """One instance's operators, with one BLAS thread (the factorizations are
+    small, and the worker processes already fill the host's cores); returns
+    the operators and the build's wall and CPU seconds."""
+    from threadpoolctl import threadpool_limits
     from paper_2309_03347_amd import operators
-    return operators.build(w)
+    t0, c0 = time.perf_counter(), time.process_time()
+    with threadpool_limits(limits=1):
+        o = operators.build(w)
+    return o, time.perf_counter() - t0, time.process_time() - c0
 
 
 def _batch_graph_leg(solvers, args):
@@ -250,23 +259,28 @@ def _batch_graph_leg(solvers, args):
         for i, g in enumerate(graphs):
             with torch.cuda.stream(streams[i % nst]):
                 g.replay()
-    batched_step()             # one untimed round
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for r in range(args.graph_steps):
-        batched_step()
-        print(f"graph batched step {r} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def timed(step, label):
+        step()                 # one untimed round
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(args.graph_steps):
+            step()
+            print(f"{label} batched step {r} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = timed(batched_step, "per-instance graphs")
     infos = [native.read_step_info(b) for b in bufs]
-    return dict(value=len(graphs) * args.graph_steps / dt, unit="instance-steps/s",
-                ms_per_batched_step=1e3 * dt / args.graph_steps, instances=len(graphs),
-                sweeps=args.graph_sweeps, not_captured=len(failed), failed=failed[:4],
-                status_counts={str(st): sum(1 for x in infos if x["status"] == st)
-                               for st in sorted(set(x["status"] for x in infos))},
-                streams=nst, grid_cap=256 // nst,
-                note="per-instance graphs of the fixed-rank step at the ranks the adaptive "
-                     "steps reached, replayed round-robin on the streams")
+    out = dict(value=len(graphs) * args.graph_steps / dt, unit="instance-steps/s",
+               ms_per_batched_step=1e3 * dt / args.graph_steps, instances=len(graphs),
+               sweeps=args.graph_sweeps, not_captured=len(failed), failed=failed[:4],
+               status_counts={str(st): sum(1 for x in infos if x["status"] == st)
+                              for st in sorted(set(x["status"] for x in infos))},
+               streams=nst, grid_cap=256 // nst,
+               note="per-instance graphs of the fixed-rank step at the ranks the adaptive "
+                    "steps reached, replayed round-robin on the streams")
+    return out
 
 
 def _graph_leg(s, args):
@@ -335,32 +349,44 @@ def _bench_batch(args):
     from paper_2309_03347_amd.solver import KeffSolver, step_batched
     wls = W.batch_instances(args.instances)
     t0 = time.perf_counter()
-    ops = []
+    ops, build_wall, build_cpu = [], [], []
     def note():
         if len(ops) % 16 == 0 or len(ops) == len(wls):
             print(f"operators of {len(ops)} / {len(wls)} instances built "
                   f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     if args.build_workers > 1:
         # fresh worker processes (no threads inherited from this one), one
-        # BLAS thread each
+        # BLAS / OpenMP thread each
         import multiprocessing as mp
-        prev = os.environ.get("OMP_NUM_THREADS")
-        os.environ["OMP_NUM_THREADS"] = "1"
+        keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+        prev = {k: os.environ.get(k) for k in keys}
+        for k in keys:
+            os.environ[k] = "1"
         ctx = mp.get_context("spawn")
-        with cf.ProcessPoolExecutor(max_workers=args.build_workers, mp_context=ctx) as ex:
-            for o in ex.map(_build_ops, wls, chunksize=2):
-                ops.append(o)
-                note()
-        if prev is None:
-            os.environ.pop("OMP_NUM_THREADS", None)
-        else:
-            os.environ["OMP_NUM_THREADS"] = prev
+        try:
+            with cf.ProcessPoolExecutor(max_workers=args.build_workers, mp_context=ctx) as ex:
+                for o, tw, tc in ex.map(_build_ops, wls, chunksize=2):
+                    ops.append(o)
+                    build_wall.append(tw)
+                    build_cpu.append(tc)
+                    note()
+        finally:
+            for k, v in prev.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
     else:
         for w in wls:
-            ops.append(_build_ops(w))
+            o, tw, tc = _build_ops(w)
+            ops.append(o)
+            build_wall.append(tw)
+            build_cpu.append(tc)
             note()
     t_ops = time.perf_counter() - t0
-    print(f"operators built for {len(wls)} instances in {t_ops:.1f} s", file=sys.stderr, flush=True)
+    print(f"operators built for {len(wls)} instances in {t_ops:.1f} s (per instance: "
+          f"{sum(build_wall):.1f} s wall, {sum(build_cpu):.1f} s CPU in total)",
+          file=sys.stderr, flush=True)
     solvers = []
     for w, o in zip(wls, ops):
         solvers.append(KeffSolver(w, rmax=w.rmax, ops=o))
@@ -430,7 +456,9 @@ def _bench_batch(args):
         "dtype": "f64", "data": "synthetic (seeded)",
         "config": {"workload": "batch256_uneven", "description": WORKLOADS["batch256_uneven"][1],
                    "instances": len(solvers), "streams": args.streams,
-                   "setup_seconds": setup},
+                   "setup_seconds": setup, "operator_build_seconds": t_ops,
+                   "operator_build_cpu_seconds_summed": sum(build_cpu),
+                   "build_workers": args.build_workers},
         "max_rank": int(max(max(s.native.ranks()) for s in solvers)),
         "graph_step": graph,
         "roofline": roofline,
@@ -545,9 +573,10 @@ def main():
     mixed = None
     if not args.no_mixed:
         # the same workload in the mixed mode: local GMRES cycles on FP32 (persistent
-        # kernel) or with BF16 matrix-core products (multi-launch GMRES), each cycle
-        # refining the FP64 local residual
-        sm = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode, ops=s.ops, precision=2)
+        # kernel) or with BF16 / FP16 matrix-core products (multi-launch GMRES), each
+        # cycle refining the FP64 local residual
+        sm = KeffSolver(wl, rmax=rmax, rhs_mode=args.rhs_mode, ops=s.ops,
+                        precision=args.mixed_precision)
         for _ in range(args.warmup):
             sm.step()
         torch.cuda.synchronize()
@@ -563,7 +592,9 @@ def main():
                      k_rel_diff_vs_fp64=abs(hm[-1].k - hist[len(hm) - 1].k) / abs(hist[len(hm) - 1].k),
                      local_iters_last=hm[-1].local_iters,
                      fp64_local_iters_last=hist[len(hm) - 1].local_iters,
-                     dtype="bf16 matrix-core products (fp32 accumulation) and fp32 Krylov "
+                     precision=args.mixed_precision,
+                     dtype=("bf16" if args.mixed_precision == 2 else "block-scaled fp16") +
+                           " matrix-core products (fp32 accumulation) and fp32 Krylov "
                            "cycles in refined local solves; fp64 residuals, interfaces, "
                            "QR / SVD, k")
         sm.close()

@@ -169,7 +169,11 @@ typedef struct {
                            method 2 for systems it cannot hold) runs its operator products
                            on the BF16 matrix cores with FP32 accumulation inside each
                            restart cycle (a cycle ends at a 1e-2 reduction), with the FP64
-                           residual at every restart; all converge in FP64 to tol */
+                           residual at every restart; 3 as 2 with the products on the FP16
+                           matrix cores, each operand row / column scaled by a power of two
+                           per 32-deep block of the contraction before the cast (FP32
+                           accumulation, the scales multiplied back); all converge in FP64
+                           to tol.  Other values: TT_E_ARG */
 } tt_solve_opts;
 
 typedef struct {
@@ -186,7 +190,13 @@ size_t tt_local_solve_workspace(const tt_local* sys, const tt_solve_opts* opts);
  * (the matrix-vector product inside the local Krylov solve, Section 3.3), as
  * three contractions: PhiL with x, the core, PhiR.  sys->f is not used.
  * precision 0: FP64; 2: the contractions on the BF16 matrix cores (operands
- * rounded to BF16, FP32 accumulation, FP64 result).  x [ra][n][rc] and y
+ * rounded to BF16, FP32 accumulation, FP64 result); 3: on the FP16 matrix
+ * cores, every row of the left and column of the right operand of each
+ * contraction divided, per 32-deep block of the contracted index, by the
+ * power of two just above its largest magnitude before the cast (entries in
+ * (-1, 1)), FP32 accumulation with the scales multiplied back, FP64 result;
+ * as with BF16, operands and results are held to FP32's range.  Other values:
+ * TT_E_ARG.  x [ra][n][rc] and y
  * [ra][m][rc] are device arrays; y is overwritten.  `ws` at least
  * tt_local_apply_workspace(sys) bytes.  Synchronizes `stream`.
  */
@@ -288,7 +298,8 @@ typedef struct {
   int32_t gmres_max_iter;
   int32_t direct_max;    /* local systems up to this size use dense LU */
   int32_t precision;     /* local GMRES: 0 FP64, 1 mixed (FP32 Arnoldi, FP64 refinement),
-                            2 mixed with BF16 matrix-core products in the multi-launch GMRES
+                            2 mixed with BF16 matrix-core products in the multi-launch GMRES,
+                            3 the same with block-scaled FP16 products
                             (as tt_solve_opts.precision); everything else in the step
                             (interfaces, QR, SVD, k) stays FP64 */
   /* Sweeping while the rank cap binds (the truncation error then exceeds

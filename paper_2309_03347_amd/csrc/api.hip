@@ -97,9 +97,9 @@ LocalSolveOpts solve_opts_from(const tt_solve_opts* o) {
     so.max_iter = o->max_iter > 0 ? o->max_iter : 1000;
     so.restart = o->restart > 0 ? o->restart : 80;
     so.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
-    TT_REQUIRE(o->precision >= 0 && o->precision <= 2, "precision must be 0, 1 or 2");
+    TT_REQUIRE(o->precision >= 0 && o->precision <= 3, "precision must be 0, 1, 2 or 3");
     so.mixed = o->precision >= 1;
-    so.lowp = o->precision == 2;
+    so.lowp = o->precision >= 2 ? o->precision : 0;
   }
   return so;
 }
@@ -212,6 +212,7 @@ tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* w
     Bump b;
     b.base = (char*)ws;
     b.cap = ws_bytes;
+    FactScope fs(b.d(kFactDoubles), kFactDoubles);
     round_tt((hipStream_t)stream, t, tol, rmax, rel_err, b);
     TT_HIP(hipStreamSynchronize((hipStream_t)stream));
     for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];
@@ -227,6 +228,7 @@ tt_status tt_orth_right(tt_vec* x, void* ws, size_t ws_bytes, tt_stream stream) 
     Bump b;
     b.base = (char*)ws;
     b.cap = ws_bytes;
+    FactScope fs(b.d(kFactDoubles), kFactDoubles);
     orth_right((hipStream_t)stream, t, b);
     TT_HIP(hipStreamSynchronize((hipStream_t)stream));
     for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];
@@ -288,7 +290,8 @@ tt_status tt_local_apply(const tt_local* sys, const double* x, double* y, int32_
     TT_REQUIRE(sys->ra >= 1 && sys->RL >= 1 && sys->m >= 1 && sys->n >= 1 && sys->RR >= 1 &&
                    sys->rc >= 1,
                "dimensions must be >= 1");
-    TT_REQUIRE(precision == 0 || precision == 2, "precision must be 0 (FP64) or 2 (BF16)");
+    TT_REQUIRE(precision == 0 || precision == 2 || precision == 3,
+               "precision must be 0 (FP64), 2 (BF16) or 3 (FP16)");
     if (ws_bytes < tt_local_apply_workspace(sys))
       throw CapacityError{"workspace smaller than tt_local_apply_workspace"};
     hipStream_t s = (hipStream_t)stream;
@@ -301,8 +304,8 @@ tt_status tt_local_apply(const tt_local* sys, const double* x, double* y, int32_
     permute_op(s, sys->A, sys->RL, sys->m, sys->n, sys->RR, Ap);
     LocalOp op = local_op_from(sys);
     op.Ap = Ap;
-    if (precision == 2)
-      local_apply_lp(s, op, x, y, 1.0, 0.0, T1, T2);
+    if (precision >= 2)
+      local_apply_lp(s, op, x, y, 1.0, 0.0, T1, T2, precision == 3);
     else
       local_apply(s, op, x, y, 1.0, 0.0, T1, T2);
     TT_HIP(hipStreamSynchronize(s));

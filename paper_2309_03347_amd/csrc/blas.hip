@@ -10,6 +10,8 @@ namespace ttnt {
 thread_local int64_t g_launches = 0;
 thread_local double* g_splitk_buf = nullptr;
 thread_local size_t g_splitk_cap = 0;
+thread_local double* g_fact_buf = nullptr;
+thread_local size_t g_fact_cap = 0;
 
 namespace {
 

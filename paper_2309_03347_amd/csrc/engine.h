@@ -106,9 +106,10 @@ struct LocalOp {
 };
 void local_apply(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
                  double beta, double* T1, double* T2);
-// The same product with its GEMMs on the BF16 matrix cores (FP32 accumulation).
+// The same product with its GEMMs on the BF16 (f16 false) or block-scaled FP16
+// (f16 true) matrix cores, FP32 accumulation.
 void local_apply_lp(hipStream_t s, const LocalOp& op, const double* v, double* y, double alpha,
-                    double beta, double* T1, double* T2);
+                    double beta, double* T1, double* T2, bool f16);
 
 struct LocalSolveOpts {
   int method = 0;          // 0 auto, 1 dense LU, 2 GMRES (persistent), 3 block LU, 4 GMRES (per-stage launches)
@@ -121,8 +122,9 @@ struct LocalSolveOpts {
   bool mixed = false;      // persistent GMRES: FP32 Arnoldi, FP64 residual refinement
   double inner_tol = 1e-5; // mixed: an FP32 cycle ends once its residual fell by this factor
   bool persistent = true;  // GMRES may use the persistent kernel (false: multi-launch only)
-  bool lowp = false;       // multi-launch GMRES: operator products on the BF16 matrix cores
-                           // inside each restart cycle, FP64 residual at every restart
+  int lowp = 0;            // multi-launch GMRES: operator products on the matrix cores inside
+                           // each restart cycle (2 BF16, 3 block-scaled FP16; 0 off), FP64
+                           // residual at every restart
   double inner_tol_lp = 1e-2;  // lowp: a cycle ends once its residual fell by this factor
   // Set for solves inside a step that must not wait for the device: a
   // persistent GMRES solve copies its 5-double info there (device to device)

@@ -118,6 +118,7 @@ size_t round_ws_bytes(const TTv& x) {
   b.d(svd_need + 512);
   b.d(4);         // scalars
   b.i(4);
+  b.d(kFactDoubles);   // tall-QR scratch of the API calls (g_fact_buf)
   return b.used + 4096;
 }
 
@@ -321,8 +322,8 @@ void local_apply(hipStream_t s, const LocalOp& o, const double* v, double* y, do
 }
 
 void local_apply_lp(hipStream_t s, const LocalOp& o, const double* v, double* y, double alpha,
-                    double beta, double* T1, double* T2) {
-  local_apply_with(gemm_bf16, s, o, v, y, alpha, beta, T1, T2);
+                    double beta, double* T1, double* T2, bool f16) {
+  local_apply_with(f16 ? gemm_f16 : gemm_bf16, s, o, v, y, alpha, beta, T1, T2);
 }
 
 static int pick_method(const LocalOp& op, const LocalSolveOpts& o) {
@@ -499,7 +500,8 @@ LocalSolveResult local_solve(hipStream_t s, const LocalOp& op, const double* f, 
         const int j0 = j;
         for (int q = 0; q < kCheck && j < m && total < o.max_iter; ++q, ++j, ++total) {
           if (o.lowp)
-            local_apply_lp(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
+            local_apply_lp(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2,
+                           o.lowp == 3);
           else
             local_apply(s, op, V + (int64_t)j * N, V + (int64_t)(j + 1) * N, 1.0, 0.0, T1, T2);
           arnoldi_mwg(s, V, N, j, Hc, m + 1, cs, sn, g, resv, awork);

@@ -11,6 +11,27 @@ extern thread_local int64_t g_launches;
 // disables the split).  Capacity in doubles.
 extern thread_local double* g_splitk_buf;
 extern thread_local size_t g_splitk_cap;
+// Scratch of the tall QR by row blocks (qr), set like the split-K buffer by
+// the caller that owns it; null leaves tall matrices that do not fit in LDS
+// to the one-workgroup global-memory QR.  Capacity in doubles; kFactDoubles
+// covers every row-block plan (2 nb n^2 <= 2 kTallLdsDoubles).
+extern thread_local double* g_fact_buf;
+extern thread_local size_t g_fact_cap;
+constexpr size_t kTallLdsDoubles = 20480;   // 160 KiB of LDS in doubles
+constexpr size_t kFactDoubles = 2 * kTallLdsDoubles + 1024;
+// Points g_fact_buf at a buffer for the lifetime of the object.
+struct FactScope {
+  double* prev_buf;
+  size_t prev_cap;
+  FactScope(double* p, size_t cap) : prev_buf(g_fact_buf), prev_cap(g_fact_cap) {
+    g_fact_buf = p;
+    g_fact_cap = cap;
+  }
+  ~FactScope() {
+    g_fact_buf = prev_buf;
+    g_fact_cap = prev_cap;
+  }
+};
 
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]; row-major, op = transpose if flag.
 // op(A) is M x K, op(B) is K x N.
@@ -23,6 +44,12 @@ void gemm(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha, co
 void gemm_bf16(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
                const double* A, int lda, int64_t sA, const double* B, int ldb, int64_t sB,
                double beta, double* C, int ldc, int64_t sC, int batch = 1);
+// The same product on the FP16 matrix cores: each row of op(A) and column of
+// op(B) scaled by a power of two per 32-deep k block before the cast, FP32
+// accumulation with the scales multiplied back, FP64 result (lowp.hip).
+void gemm_f16(hipStream_t s, bool ta, bool tb, int M, int N, int K, double alpha,
+              const double* A, int lda, int64_t sA, const double* B, int ldb, int64_t sB,
+              double beta, double* C, int ldc, int64_t sC, int batch = 1);
 // C[b][m][n] = alpha * sum_s P[s][b][m][n] + beta * C[b][m][n], s in order (split-K partials
 // of nsplit x batch dense M x N blocks).
 void splitk_reduce(hipStream_t s, const double* P, int nsplit, int batch, int M, int N,

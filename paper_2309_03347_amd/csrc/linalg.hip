@@ -227,6 +227,39 @@ __global__ __launch_bounds__(WG) void svd_kernel(const double* __restrict__ G, i
   }
 }
 
+// Sign gauge of a thin SVD's left factor: column j of U (m rows, row stride
+// ldu) gets its largest-magnitude entry positive (the lowest row on ties), and
+// column j of V (nv rows, row stride ldv) is flipped with it.  One workgroup
+// of 256 threads per column.
+__global__ __launch_bounds__(256) void col_gauge_kernel(double* __restrict__ U, int m, int ldu,
+                                                        double* __restrict__ V, int nv, int ldv) {
+  __shared__ double sb[4], ss[4];
+  __shared__ int si[4];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double best = -1.0, sgn = 1.0;
+  int bi = 0x7fffffff;
+  for (int i = tid; i < m; i += 256) {
+    const double x = U[(int64_t)i * ldu + j];
+    if (fabs(x) > best) { best = fabs(x); sgn = x < 0.0 ? -1.0 : 1.0; bi = i; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const double os = __shfl_xor(sgn, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; sgn = os; bi = oi; }
+  }
+  if (lane == 0) { sb[w] = best; ss[w] = sgn; si[w] = bi; }
+  __syncthreads();
+  double b = sb[0], g = ss[0];
+  int ib = si[0];
+  for (int q = 1; q < 4; ++q)
+    if (sb[q] > b || (sb[q] == b && si[q] < ib)) { b = sb[q]; g = ss[q]; ib = si[q]; }
+  if (g < 0.0) {
+    for (int i = tid; i < m; i += 256) U[(int64_t)i * ldu + j] = -U[(int64_t)i * ldu + j];
+    for (int e = tid; e < nv; e += 256) V[(int64_t)e * ldv + j] = -V[(int64_t)e * ldv + j];
+  }
+}
+
 __global__ void trunc_rank_kernel(const double* __restrict__ S, int n, double tol, double dm1,
                                   const double* normsq, int rmax, int* rank, double* discard) {
   if (threadIdx.x != 0) return;
@@ -737,11 +770,20 @@ __device__ void hh_form_q(double* A, int m, int n, int ld, const double* tau, do
 // Element (i, c) of the input is Ag[i ars + c acs] and element (i, c) of Q
 // is written to Qg[i qrs + c qcs], so a transposed operand or result needs no
 // separate transpose (the input is fully read into LDS before Q is written,
-// so Qg may overlap Ag).
+// so Qg may overlap Ag).  Workgroup b factors rows [b mb, min(m, (b + 1) mb))
+// on its own, its R at R + b rbs (one workgroup: mb = m).
 __global__ __launch_bounds__(WS) void qr_lds_kernel(const double* Ag, int m, int n, int64_t ars,
                                                     int64_t acs, double* Qg, int64_t qrs,
-                                                    int64_t qcs, double* __restrict__ R, int ldr) {
+                                                    int64_t qcs, double* __restrict__ R, int ldr,
+                                                    int mb, int64_t rbs) {
   extern __shared__ double sm[];
+  {
+    const int64_t r0 = (int64_t)blockIdx.x * mb;
+    Ag += r0 * ars;
+    Qg += r0 * qrs;
+    R += blockIdx.x * rbs;
+    m = min(mb, m - (int)r0);
+  }
   const int ld = odd_ld(m), k = min(m, n), tid = threadIdx.x;
   double* A = sm;
   double* tau = A + (int64_t)ld * n;
@@ -1218,15 +1260,117 @@ bool qr_t(hipStream_t s, const double* A, int m, int n, int64_t ars, int64_t acs
   if (m <= 0 || n <= 0) return true;
   if (qr_lds_doubles(m, n) * 8 > (size_t)lds_limit()) return false;
   ++g_launches;
-  qr_lds_kernel<<<1, WS, qr_lds_doubles(m, n) * 8, s>>>(A, m, n, ars, acs, Q, qrs, qcs, R, ldr);
+  qr_lds_kernel<<<1, WS, qr_lds_doubles(m, n) * 8, s>>>(A, m, n, ars, acs, Q, qrs, qcs, R, ldr,
+                                                        m, 0);
   TT_HIP(hipGetLastError());
   return true;
 }
+
+namespace {
+// Tall factorizations whose matrix does not fit in LDS, by row blocks (TSQR):
+// A (m x n) = diag(Q_1 .. Q_nb) [R_1; ..; R_nb], every block of at least n
+// rows factored in LDS by a workgroup of its own (Q_b written over A_b), the
+// stacked R_b (nb n x n) factored in LDS once more, [R_b] = Q2 R, so that
+// A = (diag(Q_b) Q2) R.  Both levels are Householder QR with diag(R) >= 0, so
+// the factors are those of one Householder QR of A up to rounding.
+struct TallPlan {
+  int nb = 0, mb = 0, last = 0;   // blocks, rows per block, rows of the last
+};
+
+bool tall_plan(int m, int n, TallPlan& p) {
+  if (n < 1 || m <= 2 * n) return false;
+  const size_t L = (size_t)lds_limit();
+  auto fits = [&](int rows) { return qr_lds_doubles(rows, n) * 8 <= L; };
+  if (fits(m) || !fits(2 * n)) return false;
+  int mmax = 2 * n;
+  while (mmax < m && fits(mmax + 1)) ++mmax;
+  p.nb = cdiv(m, mmax);
+  p.mb = cdiv(m, p.nb);
+  p.last = m - (p.nb - 1) * p.mb;
+  return p.last >= n && fits(p.nb * n);
+}
+
+bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
+  return a < b + nb && b < a + na;
+}
+
+// Q_b over the blocks of A in place, R_b at Rs + b n n (n x n each).
+void tall_blocks(hipStream_t s, double* A, int m, int n, int lda, const TallPlan& p,
+                 double* Rs) {
+  ++g_launches;
+  qr_lds_kernel<<<p.nb, WS, qr_lds_doubles(p.mb, n) * 8, s>>>(A, m, n, lda, 1, A, lda, 1, Rs, n,
+                                                               p.mb, (int64_t)n * n);
+  TT_HIP(hipGetLastError());
+}
+
+// C_b = A_b W_b for every row block (W_b at W + b n n, n x n).
+void tall_apply(hipStream_t s, const double* A, int n, int lda, const TallPlan& p,
+                const double* W, double* C, int ldc) {
+  const int full = p.last == p.mb ? p.nb : p.nb - 1;
+  gemm(s, false, false, p.mb, n, n, 1.0, A, lda, (int64_t)p.mb * lda, W, n, (int64_t)n * n, 0.0,
+       C, ldc, (int64_t)p.mb * ldc, full);
+  if (full < p.nb) {
+    const int64_t r0 = (int64_t)full * p.mb;
+    gemm(s, false, false, p.last, n, n, 1.0, A + r0 * lda, lda, 0, W + (int64_t)full * n * n, n,
+         0, 0.0, C + r0 * ldc, ldc, 0);
+  }
+}
+
+bool svd_lds_ok(int m, int n) {
+  const int npair = (n + 1) / 2;
+  int lp = 64;
+  while (lp > 4 && npair * lp > WS) lp >>= 1;
+  return npair * lp <= WS && svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit();
+}
+
+// QR of a tall A by row blocks; needs 2 nb n^2 doubles of scratch and Q apart
+// from A.  False (nothing launched) when the plan does not apply.
+bool qr_tall(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R,
+             int ldr, double* ws, size_t ws_doubles) {
+  TallPlan p;
+  if (!ws || !tall_plan(m, n, p)) return false;
+  const size_t nn = (size_t)n * n;
+  if (2 * (size_t)p.nb * nn > ws_doubles) return false;
+  if (overlaps(A, (int64_t)(m - 1) * lda + n, Q, (int64_t)(m - 1) * ldq + n)) return false;
+  double* Rs = ws;
+  double* Q2 = ws + p.nb * nn;
+  tall_blocks(s, A, m, n, lda, p, Rs);
+  TT_REQUIRE(qr_t(s, Rs, p.nb * n, n, n, 1, Q2, n, 1, R, ldr), "stacked R factors exceed LDS");
+  tall_apply(s, A, n, lda, p, Q2, Q, ldq);
+  return true;
+}
+
+// Thin SVD of a tall G by row blocks: G = (diag(Q_b) Q2) R, R = U_R S V^T in
+// LDS, U = diag(Q_b) (Q2 U_R), then the sign gauge of U (V flipped with it).
+bool svd_tall(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
+              double* V, int ldv, double* ws, size_t ws_doubles) {
+  TallPlan p;
+  if (!ws || !tall_plan(m, n, p) || !svd_lds_ok(n, n)) return false;
+  const size_t nn = (size_t)n * n;
+  if (3 * (size_t)p.nb * nn + 2 * nn > ws_doubles) return false;
+  if (overlaps(G, (int64_t)(m - 1) * ldg + n, U, (int64_t)(m - 1) * ldu + n)) return false;
+  double* Rs = ws;
+  double* Q2 = Rs + p.nb * nn;
+  double* W = Q2 + p.nb * nn;
+  double* Rf = W + p.nb * nn;
+  double* UR = Rf + nn;
+  tall_blocks(s, G, m, n, ldg, p, Rs);
+  TT_REQUIRE(qr_t(s, Rs, p.nb * n, n, n, 1, Q2, n, 1, Rf, n), "stacked R factors exceed LDS");
+  TT_REQUIRE(svd_t(s, Rf, n, n, n, 1, UR, n, 1, S, V, ldv, 1), "R factor exceeds LDS");
+  gemm(s, false, false, p.nb * n, n, n, 1.0, Q2, n, 0, UR, n, 0, 0.0, W, n, 0);
+  tall_apply(s, G, n, ldg, p, W, U, ldu);
+  ++g_launches;
+  col_gauge_kernel<<<n, 256, 0, s>>>(U, m, ldu, V, n, ldv);
+  TT_HIP(hipGetLastError());
+  return true;
+}
+}  // namespace
 
 void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R, int ldr,
         double* tau) {
   if (m <= 0 || n <= 0) return;
   if (qr_t(s, A, m, n, lda, 1, Q, ldq, 1, R, ldr)) return;
+  if (qr_tall(s, A, m, n, lda, Q, ldq, R, ldr, g_fact_buf, g_fact_cap)) return;
   ++g_launches;
   const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
   qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
@@ -1234,7 +1378,15 @@ void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, dou
   TT_HIP(hipGetLastError());
 }
 
-size_t svd_work_doubles(int m, int n) { return (size_t)n * m + (size_t)n * n + 2 * (size_t)n; }
+// Scratch of the one-workgroup global-memory SVD.
+static size_t svd_kernel_doubles(int m, int n) {
+  return (size_t)n * m + (size_t)n * n + 2 * (size_t)n;
+}
+// That, plus the row-block form's scratch: 3 nb n^2 + 2 n^2 with nb n stacked
+// rows within LDS (at most kTallLdsDoubles / n of them).
+size_t svd_work_doubles(int m, int n) {
+  return svd_kernel_doubles(m, n) + 3 * kTallLdsDoubles + 2 * (size_t)n * n;
+}
 
 bool svd_t(hipStream_t s, const double* G, int m, int n, int64_t gr, int64_t gc, double* U,
            int64_t ur, int64_t uc, double* S, double* V, int64_t vr, int64_t vc) {
@@ -1264,8 +1416,9 @@ void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, do
   if (m <= 0 || n <= 0) return;
   TT_REQUIRE(m >= n, "svd expects m >= n");
   if (svd_t(s, G, m, n, ldg, 1, U, ldu, 1, S, V, ldv, 1)) return;
+  if (svd_tall(s, G, m, n, ldg, U, ldu, S, V, ldv, work, svd_work_doubles(m, n))) return;
   ++g_launches;
-  const size_t need = svd_work_doubles(m, n);
+  const size_t need = svd_kernel_doubles(m, n);
   const bool lds = need <= (size_t)kLdsDoubles;
   svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
   TT_HIP(hipGetLastError());

@@ -64,6 +64,7 @@ struct Solver {
   size_t rw_cap = 0;
   static constexpr size_t kSplitK = (size_t)1 << 21;   // split-K partials (doubles)
   double* splitk = nullptr;
+  double* factw = nullptr;     // tall-QR scratch (g_fact_buf while the solver runs)
   double *scal = nullptr, *resarr = nullptr;
   double* kry_dev = nullptr;   // 5 per core: persistent GMRES info of the asynchronous step
   int* irank = nullptr;

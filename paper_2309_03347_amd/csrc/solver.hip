@@ -237,6 +237,7 @@ void Solver::plan(Bump& b) {
     rw_cap = need + 4096;
   }
   splitk = b.d(kSplitK);
+  factw = b.d(kFactDoubles);
   scal = b.d(64);
   resarr = b.d(dd + 8);
   kry_dev = b.d(5 * (int64_t)dd + 8);
@@ -252,6 +253,8 @@ Solver::~Solver() {
 void Solver::enter() {
   g_splitk_buf = splitk;
   g_splitk_cap = kSplitK;
+  g_fact_buf = factw;
+  g_fact_cap = kFactDoubles;
   g_probe = probe.active ? &probe : nullptr;
   g_launches = launch_acc;
 }
@@ -260,6 +263,8 @@ void Solver::leave() {
   launch_acc = g_launches;
   g_splitk_buf = nullptr;
   g_splitk_cap = 0;
+  g_fact_buf = nullptr;
+  g_fact_cap = 0;
   g_probe = nullptr;
 }
 
@@ -294,7 +299,7 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o, void* ext, siz
   lso.restart = o->gmres_restart > 0 ? o->gmres_restart : 80;
   lso.direct_max = o->direct_max >= 0 ? o->direct_max : 256;
   lso.eta = 0.0;
-  TT_REQUIRE(o->precision >= 0 && o->precision <= 2, "precision must be 0, 1 or 2");
+  TT_REQUIRE(o->precision >= 0 && o->precision <= 3, "precision must be 0, 1, 2 or 3");
   TT_REQUIRE(o->min_sweeps >= 0 && o->cap_eta >= 0.0 && o->cap_eta < 1.0 && o->stall >= 0.0 &&
                  o->stall <= 1.0,
              "bad sweep-stopping options");
@@ -302,7 +307,7 @@ void Solver::create(const tt_problem* p, const tt_solver_opts* o, void* ext, siz
   if (o->cap_eta > 0.0) cap_eta = o->cap_eta;
   if (o->stall > 0.0) stall = o->stall;
   lso.mixed = o->precision >= 1;
-  lso.lowp = o->precision == 2;
+  lso.lowp = o->precision >= 2 ? o->precision : 0;
   TT_REQUIRE(o->krylov_path == 0 || o->krylov_path == 1, "krylov_path must be 0 or 1");
   lso.persistent = o->krylov_path == 0;
   // identity operator (explicit mode right-hand side)

@@ -355,7 +355,8 @@ def tt_local_solve(phiL, A, phiR, f, x0, method: int = 0, tol: float = 1e-12,
 
 
 def tt_local_apply(phiL, A, phiR, x, precision: int = 0):
-    """y = (PhiL (x) A (x) PhiR) x; tensors are float64 CUDA tensors.  precision 2: BF16."""
+    """y = (PhiL (x) A (x) PhiR) x; tensors are float64 CUDA tensors.  precision 2:
+    BF16 matrix-core contractions, 3: block-scaled FP16 ones (FP32 accumulation)."""
     torch = _torch()
     ra, RL, _ = phiL.shape
     RL2, m, n, RR = A.shape

@@ -107,6 +107,35 @@ def test_local_solve_rejects_unknown_method():
         assert b"method" in native.lib().tt_last_error()
 
 
+def test_precision_outside_the_defined_modes_is_rejected():
+    # 0 FP64, 1 mixed, 2 BF16 products, 3 block-scaled FP16 products; the
+    # product alone has no mode 1
+    lib = native.lib()
+    sysd = native.TTLocal(2, 1, 3, 3, 1, 2, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), ctypes.c_void_p(8))
+    info = native.TTSolveInfo()
+    for precision in (-1, 4):
+        opts = native.TTSolveOpts(0, 1e-10, 10, 10, 64, precision)
+        st = lib.tt_local_solve(ctypes.byref(sysd), ctypes.c_void_p(8), ctypes.byref(opts),
+                                ctypes.byref(info), ctypes.c_void_p(8), 1 << 30, None)
+        assert st == native.TT_E_ARG, precision
+        assert b"precision" in lib.tt_last_error()
+    for precision in (-1, 1, 4):
+        st = lib.tt_local_apply(ctypes.byref(sysd), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                precision, ctypes.c_void_p(8), 1 << 30, None)
+        assert st == native.TT_E_ARG, precision
+        assert b"precision" in lib.tt_last_error()
+    H, kh = _host_mat([2], [2], [1, 1])
+    SF, ks = _host_mat([2], [2], [1, 1])
+    cF, kc = _host_vec([2], [1, 1], [1, 1])
+    p0, kp = _host_vec([2], [1, 1], [1, 1])
+    prob = native.TTProblem(H, SF, ctypes.c_void_p(0x1000), cF, p0, 1.0)
+    opts = native.TTSolverOpts(1e-8, 4, 4, 10, 0, 0, 0.0, 40, 100, 64, 4)
+    h = ctypes.c_void_p()
+    assert lib.tt_solver_create(ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(h)) == native.TT_E_ARG
+    assert b"precision" in lib.tt_last_error()
+
+
 def test_solver_rejects_bad_options():
     lib = native.lib()
     H, kh = _host_mat([2], [2], [1, 1])

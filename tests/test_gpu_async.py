@@ -140,3 +140,52 @@ def test_capped_graphs_replay_concurrently_on_two_streams(cuda):
                 assert np.array_equal(ca, cb), (r, i)
     for s in eager + graphed:
         s.close()
+
+
+def test_one_graph_forks_instances_over_streams(cuda):
+    # three instances' fixed-rank steps captured into ONE graph: the capture
+    # stream forks to two side streams, each instance's step is recorded on
+    # one of them, and both join back before the capture ends; replaying the
+    # graph equals the same steps enqueued eagerly under the same grid cap
+    import torch
+    from paper_2309_03347_amd import native
+    wls = [W.inner_box(l=3, G=2, N=4, seed=21, rmax=64, tol=1e-10),
+           W.homogeneous(l=3, N=2, seed=3, tol=1e-10),
+           W.homogeneous(l=2, N=4, seed=5, tol=1e-10)]
+    eager = [_settled(w) for w in wls]
+    graphed = [_settled(w) for w in wls]
+    bufs_e = [native.step_info_buffer() for _ in wls]
+    bufs_g = [native.step_info_buffer() for _ in wls]
+    side = [torch.cuda.Stream() for _ in range(2)]
+    cap = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    native.set_grid_cap(128)
+    try:
+        with torch.cuda.graph(g, stream=cap):
+            for st in side:
+                st.wait_stream(cap)
+            for i, (s, b) in enumerate(zip(graphed, bufs_g)):
+                with torch.cuda.stream(side[i % 2]):
+                    s.native.step_async(b, sweeps=3)
+            for st in side:
+                cap.wait_stream(st)
+    finally:
+        native.set_grid_cap(0)
+    for r in range(2):
+        print(f"one-graph replay {r}", flush=True)
+        native.set_grid_cap(128)
+        try:
+            for s, b in zip(eager, bufs_e):
+                s.native.step_async(b, sweeps=3)
+        finally:
+            native.set_grid_cap(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(wls)):
+            assert native.read_step_info(bufs_e[i]) == native.read_step_info(bufs_g[i]), (r, i)
+            for ca, cb in zip(eager[i].psi_cores(), graphed[i].psi_cores()):
+                assert np.array_equal(ca, cb), (r, i)
+    for s in eager + graphed:
+        s.close()

@@ -53,8 +53,9 @@ def _inflate(rng, x):
     # inflated ranks up to 66: SVDs with 4 lanes per Jacobi pair
     ((4,) * 6, (3, 9, 22, 9, 3)),
     # an angle-like core of 80 directions between rank 8 and rank 64 (192
-    # inflated): QR of 640 x 192 and 3072 x 24 and SVDs of 5120 x 8 and
-    # 192 x 128 outside LDS (global-memory factorizations)
+    # inflated): QR of 640 x 192 and SVD of 192 x 128 outside LDS by the
+    # global-memory factorizations, QR of 3072 x 24 and SVD of 5120 x 8 by
+    # row blocks
     ((8, 80, 16, 8), (8, 64, 8)),
     # rank 140 (420 inflated): SVD of 144 x 144, more than 128 columns
     ((12, 12, 12, 12), (12, 140, 12)),
@@ -78,6 +79,38 @@ def test_round_recovers_exact_ranks(cuda, modes, ranks):
     for k in range(1, len(modes)):
         c = y[k].reshape(y[k].shape[0], -1)
         assert np.allclose(c @ c.T, np.eye(c.shape[0]), atol=1e-12)
+
+
+@pytest.mark.parametrize("modes,ranks,cut,bond", [
+    # QR of 5440 x 8 and SVD of 640 x 68 (the shape of the 128^3 S8 angle
+    # core's unfolding) by row blocks: three blocks in LDS, their stacked R
+    ((72, 80, 8), (68, 8), 40, 1),
+    # QR of 640 x 64 and SVD of 5120 x 8 by row blocks
+    ((8, 80, 16, 8), (8, 64, 8), 40, 2),
+])
+def test_round_by_row_blocks(cuda, modes, ranks, cut, bond):
+    # matrices too tall for LDS are factored in row blocks; the rounding keeps
+    # the tensor and its ranks, leaves right-orthonormal cores, and a rank cut
+    # on one bond equals the optimal truncation of that bond's unfolding
+    from paper_2309_03347_amd import native
+    rng = np.random.default_rng(sum(modes))
+    x = _rand_tt(rng, modes, ranks)
+    full = OT.full_vec(x)
+    d = native.DeviceTT.from_cores(x)
+    native.tt_round(d, 1e-13, 1000)
+    y = d.cores()
+    assert list(d.r[1:-1]) == list(ranks)
+    assert np.linalg.norm(OT.full_vec(y) - full) <= 1e-12 * np.linalg.norm(full)
+    for k in range(1, len(modes)):
+        c = y[k].reshape(y[k].shape[0], -1)
+        assert np.allclose(c @ c.T, np.eye(c.shape[0]), atol=1e-12), k
+    d2 = native.DeviceTT.from_cores(x)
+    native.tt_round(d2, 1e-14, cut)
+    assert d2.r[bond] == cut and max(d2.r) == max(cut, max(r for r in ranks if r <= cut))
+    s = OT.unfolding_svals(full, modes, bond)
+    best = np.sqrt((s[cut:] ** 2).sum())
+    err = np.linalg.norm(OT.full_vec(d2.cores()) - full)
+    assert abs(err - best) <= 1e-9 * best, (err, best)
 
 
 @pytest.mark.parametrize("tol", [1e-2, 1e-4, 1e-6])

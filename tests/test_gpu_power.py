@@ -109,7 +109,10 @@ def test_power_steps_32cube_four_groups_error_at_rank_caps(cuda):
 @pytest.mark.parametrize("maker", [
     lambda: W.inner_box(l=2, G=2, N=8, seed=23, rmax=256, tol=1e-10),   # angle = core 1
     lambda: W.homogeneous(l=3, N=8, seed=24, rmax=256, tol=1e-10),       # angle = core 0
-], ids=["G2_S8_angle_core1", "G1_S8_angle_core0"])
+    # eight groups: the angle core's unfoldings are 640 rows tall, factored
+    # by row blocks once its right rank passes 31 (640 x 32 exceeds LDS)
+    lambda: W.inner_box(l=2, G=8, N=8, seed=25, rmax=256, tol=1e-10),
+], ids=["G2_S8_angle_core1", "G1_S8_angle_core0", "G8_S8_angle_core1"])
 def test_power_steps_match_oracle_s8(cuda, maker):
     # 80 directions: the angle core's contractions use its structure (H
     # diagonal in the direction, S and F summing directions with the weights;
@@ -128,6 +131,7 @@ def test_power_steps_match_oracle_s8(cuda, maker):
         got = OT.full_vec(s.psi_cores())
         assert abs(rec.k - kref) <= 1e-8 * abs(kref), (step, rec.k, kref)
         assert np.linalg.norm(_unit(got) - _unit(ref)) <= 1e-6, step
+        print(f"  ranks {list(s.native.ranks())}", flush=True)
         psi, k = got, rec.k
     s.close()
 
