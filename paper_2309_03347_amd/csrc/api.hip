@@ -212,7 +212,8 @@ tt_status tt_round(tt_vec* x, double tol, int32_t rmax, double* rel_err, void* w
     Bump b;
     b.base = (char*)ws;
     b.cap = ws_bytes;
-    FactScope fs(b.d(kFactDoubles), kFactDoubles);
+    const size_t fact = fact_doubles_for(t);
+    FactScope fs(b.d(fact), fact);
     round_tt((hipStream_t)stream, t, tol, rmax, rel_err, b);
     TT_HIP(hipStreamSynchronize((hipStream_t)stream));
     for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];
@@ -228,7 +229,8 @@ tt_status tt_orth_right(tt_vec* x, void* ws, size_t ws_bytes, tt_stream stream) 
     Bump b;
     b.base = (char*)ws;
     b.cap = ws_bytes;
-    FactScope fs(b.d(kFactDoubles), kFactDoubles);
+    const size_t fact = fact_doubles_for(t);
+    FactScope fs(b.d(fact), fact);
     orth_right((hipStream_t)stream, t, b);
     TT_HIP(hipStreamSynchronize((hipStream_t)stream));
     for (int k = 0; k <= x->d; ++k) x->r[k] = t.r[k];

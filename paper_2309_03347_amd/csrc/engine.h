@@ -73,6 +73,9 @@ void release_thread_resources();
 // Blocking form of round_tt_co (synchronizes the stream).
 void round_tt(hipStream_t s, TTv& x, double tol, int rmax, double* rel_err, Bump& ws);
 size_t round_ws_bytes(const TTv& x);
+// Tall-QR scratch (doubles, g_fact_buf) for the QR sweeps of x's cores at its
+// ranks, left (r n x r') and right (n r' x r) unfoldings; at least kFactDoubles.
+size_t fact_doubles_for(const TTv& x);
 // <a, b> into a device scalar `out` (no synchronization).
 void dot_tt(hipStream_t s, const TTv& a, const TTv& b, double* out, Bump& ws);
 size_t dot_ws_bytes(const TTv& a, const TTv& b);

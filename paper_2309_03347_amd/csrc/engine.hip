@@ -101,6 +101,16 @@ int max_dim(const TTv& x) {
 
 }  // namespace
 
+size_t fact_doubles_for(const TTv& x) {
+  size_t f = kFactDoubles;
+  for (int k = 0; k < x.d; ++k) {
+    const int64_t left = (int64_t)x.r[k] * x.n[k], right = (int64_t)x.n[k] * x.r[k + 1];
+    if (left <= INT32_MAX) f = std::max(f, tall_qr_doubles((int)left, x.r[k + 1]));
+    if (right <= INT32_MAX) f = std::max(f, tall_qr_doubles((int)right, x.r[k]));
+  }
+  return f;
+}
+
 size_t round_ws_bytes(const TTv& x) {
   Bump b;
   const int64_t mc = max_core(x);
@@ -118,7 +128,7 @@ size_t round_ws_bytes(const TTv& x) {
   b.d(svd_need + 512);
   b.d(4);         // scalars
   b.i(4);
-  b.d(kFactDoubles);   // tall-QR scratch of the API calls (g_fact_buf)
+  b.d(fact_doubles_for(x));   // tall-QR scratch of the API calls (g_fact_buf)
   return b.used + 4096;
 }
 

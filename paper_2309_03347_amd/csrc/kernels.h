@@ -11,14 +11,17 @@ extern thread_local int64_t g_launches;
 // disables the split).  Capacity in doubles.
 extern thread_local double* g_splitk_buf;
 extern thread_local size_t g_splitk_cap;
-// Scratch of the tall QR by row blocks (qr), set like the split-K buffer by
-// the caller that owns it; null leaves tall matrices that do not fit in LDS
-// to the one-workgroup global-memory QR.  Capacity in doubles; kFactDoubles
-// covers every row-block plan (2 nb n^2 <= 2 kTallLdsDoubles).
+// Scratch of the tall QR by a tree of row blocks (qr), set like the split-K
+// buffer by the caller that owns it; null, or shorter than the shape needs
+// (tall_qr_doubles), leaves tall matrices that do not fit in LDS to the
+// one-workgroup global-memory QR.  Capacity in doubles.
 extern thread_local double* g_fact_buf;
 extern thread_local size_t g_fact_cap;
 constexpr size_t kTallLdsDoubles = 20480;   // 160 KiB of LDS in doubles
-constexpr size_t kFactDoubles = 2 * kTallLdsDoubles + 1024;
+constexpr size_t kFactDoubles = 2 * kTallLdsDoubles + 1024;   // the least a caller provides
+// Scratch of the row-block QR of an m x n matrix planned for kTallLdsDoubles
+// of LDS (0: the shape fits in LDS or has no row-block plan).
+size_t tall_qr_doubles(int m, int n);
 // Points g_fact_buf at a buffer for the lifetime of the object.
 struct FactScope {
   double* prev_buf;

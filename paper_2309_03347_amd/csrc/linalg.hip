@@ -1267,53 +1267,155 @@ bool qr_t(hipStream_t s, const double* A, int m, int n, int64_t ars, int64_t acs
 }
 
 namespace {
-// Tall factorizations whose matrix does not fit in LDS, by row blocks (TSQR):
-// A (m x n) = diag(Q_1 .. Q_nb) [R_1; ..; R_nb], every block of at least n
-// rows factored in LDS by a workgroup of its own (Q_b written over A_b), the
-// stacked R_b (nb n x n) factored in LDS once more, [R_b] = Q2 R, so that
-// A = (diag(Q_b) Q2) R.  Both levels are Householder QR with diag(R) >= 0, so
-// the factors are those of one Householder QR of A up to rounding.
+// Tall factorizations whose matrix does not fit in LDS, by a tree of row
+// blocks (TSQR).  Level 0 splits A (m x n) into nb_0 blocks of at least n
+// rows, each factored in LDS by a workgroup of its own (Q_b written over the
+// block, R_b into a stack of nb_0 n x n factors); level i + 1 does the same to
+// level i's stack, until a stack fits in LDS and is factored whole (or no
+// longer shrinks and is factored in global memory), S = Q_top R.  Then Q = diag(Q_b of level 0) diag(Q_b of level 1) .. Q_top,
+// formed top-down by one batched GEMM per level.  Every factorization is
+// Householder QR with diag(R) >= 0, so Q and R are those of one Householder
+// QR of A up to rounding.
+constexpr int kTallMaxLevels = 8;
+
 struct TallPlan {
-  int nb = 0, mb = 0, last = 0;   // blocks, rows per block, rows of the last
+  int levels = 0;                          // row-block levels below the top
+  int rows[kTallMaxLevels + 1] = {};       // rows split at each level, rows[levels] at the top
+  int nb[kTallMaxLevels] = {}, mb[kTallMaxLevels] = {}, last[kTallMaxLevels] = {};
+  bool top_lds = true;                     // the top stack fits in LDS (else global-memory QR)
 };
 
-bool tall_plan(int m, int n, TallPlan& p) {
-  if (n < 1 || m <= 2 * n) return false;
-  const size_t L = (size_t)lds_limit();
-  auto fits = [&](int rows) { return qr_lds_doubles(rows, n) * 8 <= L; };
-  if (fits(m) || !fits(2 * n)) return false;
-  int mmax = 2 * n;
+// lds_doubles: one workgroup's LDS, in doubles.  Levels are added while a
+// split into blocks of at least n rows that fit in LDS still shrinks the
+// stack; a top that does not fit in LDS (two stacked R factors of n > 98
+// columns already exceed 160 KiB) is factored by the global-memory QR, on
+// nb n rows instead of m.
+bool tall_plan(int m, int n, size_t lds_doubles, TallPlan& p) {
+  if (n < 1 || m <= n) return false;
+  auto fits = [&](int rows) { return qr_lds_doubles(rows, n) <= lds_doubles; };
+  if (fits(m) || !fits(n + 1)) return false;
+  int mmax = n + 1;
   while (mmax < m && fits(mmax + 1)) ++mmax;
-  p.nb = cdiv(m, mmax);
-  p.mb = cdiv(m, p.nb);
-  p.last = m - (p.nb - 1) * p.mb;
-  return p.last >= n && fits(p.nb * n);
+  int rows = m;
+  p.levels = 0;
+  while (!fits(rows) && p.levels < kTallMaxLevels) {
+    const int nb = cdiv(rows, mmax), mb = cdiv(rows, nb), last = rows - (nb - 1) * mb;
+    if (nb < 2 || last < n || (int64_t)nb * n >= rows) break;
+    const int L = p.levels;
+    p.rows[L] = rows;
+    p.nb[L] = nb;
+    p.mb[L] = mb;
+    p.last[L] = last;
+    rows = nb * n;
+    ++p.levels;
+  }
+  if (p.levels == 0) return false;
+  p.rows[p.levels] = rows;
+  p.top_lds = fits(rows);
+  return true;
+}
+
+// Scratch of the tree: the R stacks of every level, Q_top, the global QR's
+// n scale factors, and two buffers for the partial products of levels
+// 1 .. levels - 1.
+size_t tall_scratch(const TallPlan& p, int n) {
+  const size_t nn = (size_t)n * n;
+  size_t need = (size_t)p.rows[p.levels] * n + n;
+  size_t pp = 0;
+  for (int i = 0; i < p.levels; ++i) {
+    need += (size_t)p.nb[i] * nn;
+    if (i >= 1) pp = std::max(pp, (size_t)p.rows[i] * n);
+  }
+  return need + 2 * pp;
 }
 
 bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
   return a < b + nb && b < a + na;
 }
 
-// Q_b over the blocks of A in place, R_b at Rs + b n n (n x n each).
-void tall_blocks(hipStream_t s, double* A, int m, int n, int lda, const TallPlan& p,
-                 double* Rs) {
+// The one-workgroup global-memory factorizations (LDS copies when small).
+void qr_global(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R,
+               int ldr, double* tau) {
   ++g_launches;
-  qr_lds_kernel<<<p.nb, WS, qr_lds_doubles(p.mb, n) * 8, s>>>(A, m, n, lda, 1, A, lda, 1, Rs, n,
-                                                               p.mb, (int64_t)n * n);
+  const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
+  qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
+      A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
 
-// C_b = A_b W_b for every row block (W_b at W + b n n, n x n).
-void tall_apply(hipStream_t s, const double* A, int n, int lda, const TallPlan& p,
+size_t svd_kernel_doubles(int m, int n) {
+  return (size_t)n * m + (size_t)n * n + 2 * (size_t)n;
+}
+
+void svd_global(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
+                double* V, int ldv, double* work) {
+  ++g_launches;
+  const size_t need = svd_kernel_doubles(m, n);
+  const bool lds = need <= (size_t)kLdsDoubles;
+  svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
+  TT_HIP(hipGetLastError());
+}
+
+// Level i: Q_b over the blocks of A in place, R_b at Rs + b n n.
+void tall_blocks(hipStream_t s, double* A, int n, int lda, const TallPlan& p, int i,
+                 double* Rs) {
+  ++g_launches;
+  qr_lds_kernel<<<p.nb[i], WS, qr_lds_doubles(p.mb[i], n) * 8, s>>>(
+      A, p.rows[i], n, lda, 1, A, lda, 1, Rs, n, p.mb[i], (int64_t)n * n);
+  TT_HIP(hipGetLastError());
+}
+
+// Level i: C_b = A_b W_b for every row block (W_b at W + b n n, n x n).
+void tall_apply(hipStream_t s, const double* A, int n, int lda, const TallPlan& p, int i,
                 const double* W, double* C, int ldc) {
-  const int full = p.last == p.mb ? p.nb : p.nb - 1;
-  gemm(s, false, false, p.mb, n, n, 1.0, A, lda, (int64_t)p.mb * lda, W, n, (int64_t)n * n, 0.0,
-       C, ldc, (int64_t)p.mb * ldc, full);
-  if (full < p.nb) {
-    const int64_t r0 = (int64_t)full * p.mb;
-    gemm(s, false, false, p.last, n, n, 1.0, A + r0 * lda, lda, 0, W + (int64_t)full * n * n, n,
-         0, 0.0, C + r0 * ldc, ldc, 0);
+  const int mb = p.mb[i], nb = p.nb[i];
+  const int full = p.last[i] == mb ? nb : nb - 1;
+  gemm(s, false, false, mb, n, n, 1.0, A, lda, (int64_t)mb * lda, W, n, (int64_t)n * n, 0.0, C,
+       ldc, (int64_t)mb * ldc, full);
+  if (full < nb) {
+    const int64_t r0 = (int64_t)full * mb;
+    gemm(s, false, false, p.last[i], n, n, 1.0, A + r0 * lda, lda, 0, W + (int64_t)full * n * n,
+         n, 0, 0.0, C + r0 * ldc, ldc, 0);
   }
+}
+
+// The tree QR with a plan and its scratch (tall_scratch doubles); A is
+// overwritten, Q must not overlap A.
+void tall_qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R,
+             int ldr, const TallPlan& p, double* ws) {
+  const int L = p.levels;
+  double* S[kTallMaxLevels];
+  double* cur = ws;
+  for (int i = 0; i < L; ++i) {
+    S[i] = cur;
+    cur += (size_t)p.nb[i] * n * n;
+  }
+  double* Qtop = cur;
+  cur += (size_t)p.rows[L] * n;
+  double* tau = cur;
+  cur += n;
+  size_t pp = 0;
+  for (int i = 1; i < L; ++i) pp = std::max(pp, (size_t)p.rows[i] * n);
+  double* P[2] = {cur, cur + pp};
+  double* Ai = A;
+  int ldi = lda;
+  for (int i = 0; i < L; ++i) {
+    tall_blocks(s, Ai, n, ldi, p, i, S[i]);
+    Ai = S[i];
+    ldi = n;
+  }
+  if (p.top_lds)
+    TT_REQUIRE(qr_t(s, Ai, p.rows[L], n, n, 1, Qtop, n, 1, R, ldr), "top R stack exceeds LDS");
+  else
+    qr_global(s, Ai, p.rows[L], n, n, Qtop, n, R, ldr, tau);
+  const double* W = Qtop;
+  for (int i = L - 1; i >= 0; --i) {
+    const double* Ab = i == 0 ? A : S[i - 1];
+    double* out = i == 0 ? Q : P[i & 1];
+    tall_apply(s, Ab, n, i == 0 ? lda : n, p, i, W, out, i == 0 ? ldq : n);
+    W = out;
+  }
+  (void)m;
 }
 
 bool svd_lds_ok(int m, int n) {
@@ -1323,42 +1425,41 @@ bool svd_lds_ok(int m, int n) {
   return npair * lp <= WS && svd_lds_doubles(m, n) * 8 <= (size_t)lds_limit();
 }
 
-// QR of a tall A by row blocks; needs 2 nb n^2 doubles of scratch and Q apart
-// from A.  False (nothing launched) when the plan does not apply.
+// QR of a tall A by the row-block tree; false (nothing launched) when the
+// plan does not apply, the scratch is short or Q overlaps A.
 bool qr_tall(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R,
              int ldr, double* ws, size_t ws_doubles) {
   TallPlan p;
-  if (!ws || !tall_plan(m, n, p)) return false;
-  const size_t nn = (size_t)n * n;
-  if (2 * (size_t)p.nb * nn > ws_doubles) return false;
+  if (!ws || !tall_plan(m, n, (size_t)lds_limit() / 8, p)) return false;
+  if (tall_scratch(p, n) > ws_doubles) return false;
   if (overlaps(A, (int64_t)(m - 1) * lda + n, Q, (int64_t)(m - 1) * ldq + n)) return false;
-  double* Rs = ws;
-  double* Q2 = ws + p.nb * nn;
-  tall_blocks(s, A, m, n, lda, p, Rs);
-  TT_REQUIRE(qr_t(s, Rs, p.nb * n, n, n, 1, Q2, n, 1, R, ldr), "stacked R factors exceed LDS");
-  tall_apply(s, A, n, lda, p, Q2, Q, ldq);
+  tall_qr(s, A, m, n, lda, Q, ldq, R, ldr, p, ws);
   return true;
 }
 
-// Thin SVD of a tall G by row blocks: G = (diag(Q_b) Q2) R, R = U_R S V^T in
-// LDS, U = diag(Q_b) (Q2 U_R), then the sign gauge of U (V flipped with it).
+// Thin SVD of a tall G: G = Q R by the tree (Q into scratch), R = U_R S V^T in
+// LDS, U = Q U_R, then the sign gauge of U (V flipped with it).
 bool svd_tall(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, double* S,
               double* V, int ldv, double* ws, size_t ws_doubles) {
   TallPlan p;
-  if (!ws || !tall_plan(m, n, p) || !svd_lds_ok(n, n)) return false;
+  if (!ws || !tall_plan(m, n, (size_t)lds_limit() / 8, p)) return false;
   const size_t nn = (size_t)n * n;
-  if (3 * (size_t)p.nb * nn + 2 * nn > ws_doubles) return false;
+  const bool r_lds = svd_lds_ok(n, n);
+  const size_t tree = tall_scratch(p, n);
+  if ((size_t)m * n + 2 * nn + std::max(tree, r_lds ? 0 : svd_kernel_doubles(n, n)) > ws_doubles)
+    return false;
   if (overlaps(G, (int64_t)(m - 1) * ldg + n, U, (int64_t)(m - 1) * ldu + n)) return false;
-  double* Rs = ws;
-  double* Q2 = Rs + p.nb * nn;
-  double* W = Q2 + p.nb * nn;
-  double* Rf = W + p.nb * nn;
+  double* Qf = ws;
+  double* Rf = Qf + (size_t)m * n;
   double* UR = Rf + nn;
-  tall_blocks(s, G, m, n, ldg, p, Rs);
-  TT_REQUIRE(qr_t(s, Rs, p.nb * n, n, n, 1, Q2, n, 1, Rf, n), "stacked R factors exceed LDS");
-  TT_REQUIRE(svd_t(s, Rf, n, n, n, 1, UR, n, 1, S, V, ldv, 1), "R factor exceeds LDS");
-  gemm(s, false, false, p.nb * n, n, n, 1.0, Q2, n, 0, UR, n, 0, 0.0, W, n, 0);
-  tall_apply(s, G, n, ldg, p, W, U, ldu);
+  double* rest = UR + nn;
+  tall_qr(s, G, m, n, ldg, Qf, n, Rf, n, p, rest);
+  // the n x n SVD of R: in LDS, else in global memory (its scratch reuses the tree's)
+  if (r_lds)
+    TT_REQUIRE(svd_t(s, Rf, n, n, n, 1, UR, n, 1, S, V, ldv, 1), "R factor exceeds LDS");
+  else
+    svd_global(s, Rf, n, n, n, UR, n, S, V, ldv, rest);
+  gemm(s, false, false, m, n, n, 1.0, Qf, n, 0, UR, n, 0, 0.0, U, ldu, 0);
   ++g_launches;
   col_gauge_kernel<<<n, 256, 0, s>>>(U, m, ldu, V, n, ldv);
   TT_HIP(hipGetLastError());
@@ -1366,26 +1467,26 @@ bool svd_tall(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ld
 }
 }  // namespace
 
+size_t tall_qr_doubles(int m, int n) {
+  TallPlan p;
+  return tall_plan(m, n, kTallLdsDoubles, p) ? tall_scratch(p, n) : 0;
+}
+
 void qr(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R, int ldr,
         double* tau) {
   if (m <= 0 || n <= 0) return;
   if (qr_t(s, A, m, n, lda, 1, Q, ldq, 1, R, ldr)) return;
   if (qr_tall(s, A, m, n, lda, Q, ldq, R, ldr, g_fact_buf, g_fact_cap)) return;
-  ++g_launches;
-  const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
-  qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
-      A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
-  TT_HIP(hipGetLastError());
+  qr_global(s, A, m, n, lda, Q, ldq, R, ldr, tau);
 }
 
-// Scratch of the one-workgroup global-memory SVD.
-static size_t svd_kernel_doubles(int m, int n) {
-  return (size_t)n * m + (size_t)n * n + 2 * (size_t)n;
-}
-// That, plus the row-block form's scratch: 3 nb n^2 + 2 n^2 with nb n stacked
-// rows within LDS (at most kTallLdsDoubles / n of them).
+// The global-memory SVD's scratch, and at least the row-block tree's: Q
+// (m n), R and U_R, then the tree or the n x n global SVD of R.
 size_t svd_work_doubles(int m, int n) {
-  return svd_kernel_doubles(m, n) + 3 * kTallLdsDoubles + 2 * (size_t)n * n;
+  const size_t tall = tall_qr_doubles(m, n);
+  const size_t tree =
+      tall ? (size_t)m * n + 2 * (size_t)n * n + std::max(tall, svd_kernel_doubles(n, n)) : 0;
+  return std::max(svd_kernel_doubles(m, n), tree);
 }
 
 bool svd_t(hipStream_t s, const double* G, int m, int n, int64_t gr, int64_t gc, double* U,
@@ -1417,11 +1518,7 @@ void svd(hipStream_t s, double* G, int m, int n, int ldg, double* U, int ldu, do
   TT_REQUIRE(m >= n, "svd expects m >= n");
   if (svd_t(s, G, m, n, ldg, 1, U, ldu, 1, S, V, ldv, 1)) return;
   if (svd_tall(s, G, m, n, ldg, U, ldu, S, V, ldv, work, svd_work_doubles(m, n))) return;
-  ++g_launches;
-  const size_t need = svd_kernel_doubles(m, n);
-  const bool lds = need <= (size_t)kLdsDoubles;
-  svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
-  TT_HIP(hipGetLastError());
+  svd_global(s, G, m, n, ldg, U, ldu, S, V, ldv, work);
 }
 
 void trunc_rank(hipStream_t s, const double* S, int n, double tol, double dm1,

@@ -65,6 +65,7 @@ struct Solver {
   static constexpr size_t kSplitK = (size_t)1 << 21;   // split-K partials (doubles)
   double* splitk = nullptr;
   double* factw = nullptr;     // tall-QR scratch (g_fact_buf while the solver runs)
+  size_t factw_cap = 0;        // its doubles
   double *scal = nullptr, *resarr = nullptr;
   double* kry_dev = nullptr;   // 5 per core: persistent GMRES info of the asynchronous step
   int* irank = nullptr;

@@ -237,7 +237,18 @@ void Solver::plan(Bump& b) {
     rw_cap = need + 4096;
   }
   splitk = b.d(kSplitK);
-  factw = b.d(kFactDoubles);
+  {
+    // the QR shapes of every TT the solver factors, at capacity
+    factw_cap = kFactDoubles;
+    for (const std::vector<int>* cap : {&capPsi, &capX, &zr, &capV}) {
+      TTv t;
+      t.d = dd;
+      t.n = n;
+      t.r = *cap;
+      factw_cap = std::max(factw_cap, fact_doubles_for(t));
+    }
+    factw = b.d(factw_cap);
+  }
   scal = b.d(64);
   resarr = b.d(dd + 8);
   kry_dev = b.d(5 * (int64_t)dd + 8);
@@ -254,7 +265,7 @@ void Solver::enter() {
   g_splitk_buf = splitk;
   g_splitk_cap = kSplitK;
   g_fact_buf = factw;
-  g_fact_cap = kFactDoubles;
+  g_fact_cap = factw_cap;
   g_probe = probe.active ? &probe : nullptr;
   g_launches = launch_acc;
 }

@@ -87,6 +87,12 @@ def test_round_recovers_exact_ranks(cuda, modes, ranks):
     ((72, 80, 8), (68, 8), 40, 1),
     # QR of 640 x 64 and SVD of 5120 x 8 by row blocks
     ((8, 80, 16, 8), (8, 64, 8), 40, 2),
+    # SVD of 2304 x 96 by a tree of four block levels (the last stack of
+    # 192 rows in LDS), its 96 x 96 R factored in global memory
+    ((128, 288, 8), (96, 8), 60, 1),
+    # SVD of 768 x 100: three block levels, then the stack of two R factors
+    # (200 x 100, beyond LDS) in global memory
+    ((128, 96, 8), (100, 8), 60, 1),
 ])
 def test_round_by_row_blocks(cuda, modes, ranks, cut, bond):
     # matrices too tall for LDS are factored in row blocks; the rounding keeps
@@ -152,11 +158,14 @@ def test_round_rank_cap_binds(cuda):
     assert np.linalg.norm(y - full) >= best * (1 - 1e-10)
 
 
-def test_orth_right_keeps_the_tensor(cuda):
+@pytest.mark.parametrize("modes,ranks", [
+    ((8, 80, 16, 8), (8, 64, 8)),     # QR of 5120 x 8 by row blocks
+    ((128, 96, 8), (100, 8)),         # QR of 768 x 100 by a tree, global-memory top
+])
+def test_orth_right_keeps_the_tensor(cuda, modes, ranks):
     from paper_2309_03347_amd import native
     rng = np.random.default_rng(12)
-    modes = (8, 80, 16, 8)
-    x = _rand_tt(rng, modes, (8, 64, 8))
+    x = _rand_tt(rng, modes, ranks)
     full = OT.full_vec(x)
     d = native.DeviceTT.from_cores(x)
     native.tt_orth_right(d)
