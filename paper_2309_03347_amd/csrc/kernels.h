@@ -17,7 +17,9 @@ extern thread_local size_t g_splitk_cap;
 // one-workgroup global-memory QR.  Capacity in doubles.
 extern thread_local double* g_fact_buf;
 extern thread_local size_t g_fact_cap;
-constexpr size_t kTallLdsDoubles = 20480;   // 160 KiB of LDS in doubles
+// LDS a workgroup may use on gfx950, in doubles: 160 KiB less the 1 KiB kept
+// for static arrays (the dynamic LDS limit the factorization kernels get)
+constexpr size_t kTallLdsDoubles = (160 * 1024 - 1024) / 8;
 constexpr size_t kFactDoubles = 2 * kTallLdsDoubles + 1024;   // the least a caller provides
 // Scratch of the row-block QR of an m x n matrix planned for kTallLdsDoubles
 // of LDS (0: the shape fits in LDS or has no row-block plan).

@@ -12,8 +12,6 @@ namespace ttnt {
 namespace {
 
 constexpr int WG = 1024;
-// Dynamic LDS budget of the single-workgroup factorizations (doubles).
-constexpr int kLdsDoubles = 8000;
 
 // Householder QR: A (m x n) -> Q (m x k), R (k x n), k = min(m, n), diag(R) >= 0.
 __global__ __launch_bounds__(WG) void qr_kernel(double* __restrict__ Ag, int m, int n, int ldag,
@@ -1099,7 +1097,24 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
       double* yp = Y + (int64_t)p * ldn;
       double* yq = Y + (int64_t)q * ldn;
       if (valid) {
-        for (int e = l; e < n; e += Lp) {
+        // four of the lane's entries loaded ahead of their products (the
+        // sums keep their order)
+        int e = l;
+        for (; e + 3 * Lp < n; e += 4 * Lp) {
+          double x[4], y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            x[u] = yp[e + u * Lp];
+            y[u] = yq[e + u * Lp];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a = fma(x[u], x[u], a);
+            b = fma(y[u], y[u], b);
+            gg = fma(x[u], y[u], gg);
+          }
+        }
+        for (; e < n; e += Lp) {
           const double x = yp[e], y = yq[e];
           a = fma(x, x, a);
           b = fma(y, y, b);
@@ -1128,7 +1143,25 @@ __global__ __launch_bounds__(WS) void svd_lds_kernel(const double* __restrict__ 
         const double c = rsq_nr(fma(t, t, 1.0)), sn = c * t;
         double* wp = Wm + (int64_t)p * ldn;
         double* wq = Wm + (int64_t)q * ldn;
-        for (int e = l; e < n; e += Lp) {
+        int e = l;
+        for (; e + 3 * Lp < n; e += 4 * Lp) {
+          double x[4], y[4], u4[4], v4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            x[u] = yp[e + u * Lp];
+            y[u] = yq[e + u * Lp];
+            u4[u] = wp[e + u * Lp];
+            v4[u] = wq[e + u * Lp];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            yp[e + u * Lp] = c * x[u] - sn * y[u];
+            yq[e + u * Lp] = sn * x[u] + c * y[u];
+            wp[e + u * Lp] = c * u4[u] - sn * v4[u];
+            wq[e + u * Lp] = sn * u4[u] + c * v4[u];
+          }
+        }
+        for (; e < n; e += Lp) {
           const double x = yp[e], y = yq[e];
           yp[e] = c * x - sn * y;
           yq[e] = sn * x + c * y;
@@ -1243,6 +1276,10 @@ int lds_limit() {
       TT_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_solve_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(qr_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
+    TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(svd_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(lu_blocked_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, v));
     TT_HIP(hipFuncSetAttribute(
@@ -1333,11 +1370,13 @@ bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
   return a < b + nb && b < a + na;
 }
 
-// The one-workgroup global-memory factorizations (LDS copies when small).
+// The one-workgroup factorizations outside the LDS-resident forms: working
+// copies in LDS when they fit in it, else in global memory.
 void qr_global(hipStream_t s, double* A, int m, int n, int lda, double* Q, int ldq, double* R,
                int ldr, double* tau) {
   ++g_launches;
-  const bool lds = (int64_t)m * n + (int64_t)m * std::min(m, n) <= kLdsDoubles;
+  const bool lds =
+      ((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 <= (int64_t)lds_limit();
   qr_kernel<<<1, WG, lds ? (size_t)((int64_t)m * n + (int64_t)m * std::min(m, n)) * 8 : 0, s>>>(
       A, m, n, lda, Q, ldq, R, ldr, tau, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
@@ -1351,7 +1390,7 @@ void svd_global(hipStream_t s, double* G, int m, int n, int ldg, double* U, int 
                 double* V, int ldv, double* work) {
   ++g_launches;
   const size_t need = svd_kernel_doubles(m, n);
-  const bool lds = need <= (size_t)kLdsDoubles;
+  const bool lds = need * 8 <= (size_t)lds_limit();
   svd_kernel<<<1, WG, lds ? need * 8 : 0, s>>>(G, m, n, ldg, U, ldu, S, V, ldv, work, lds ? 1 : 0);
   TT_HIP(hipGetLastError());
 }
